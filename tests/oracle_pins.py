@@ -1,0 +1,326 @@
+"""Checks that tie the CPU oracle to facts fixed by the paper and by mathematics.
+
+Each ``pin_*`` function takes a loaded oracle library (``oracle.load(path)``)
+and raises ``AssertionError`` when the oracle disagrees with the fact.  They are
+run against the real oracle in ``test_oracle.py`` and against deliberately
+broken copies of it in ``test_oracle_mutations.py``, which shows that a
+plausible mistake (dropped term, wrong sign or index, swapped operands, wrong
+update order) fails at least one of them.
+
+Sources of truth used here (none re-types the oracle's own loops in FP):
+  * closed form: on a zero-ghost grid the discrete sine mode
+    sin(pi p i/(nx+1)) sin(pi q j/(ny+1)) sin(pi r k/(nz+1)) is an eigenvector
+    of the Jacobi update with eigenvalue a + 2b(cos(pi p/(nx+1)) + ...);
+  * harmonic fixed points: constant and linear fields are reproduced exactly
+    when a + 6b = 1 and the ghosts match;
+  * exact rational arithmetic (fractions.Fraction) of the Sec. 3 Jacobi and
+    Gauss-Seidel definitions on tiny grids with dyadic weights and integer data,
+    where every FP64 intermediate is exact;
+  * Young's theorem: lexicographic Gauss-Seidel on the 7-point Laplacian
+    (a consistently ordered matrix) converges asymptotically with the square
+    of the Jacobi rate, cos(pi/(n+1))^2;
+  * defect correction: m sweeps on A e = r from e = 0 added to u0 equal m
+    sweeps on u from u0 (linearity).
+"""
+from __future__ import annotations
+
+import math
+from fractions import Fraction
+
+import numpy as np
+
+import oracle
+
+EPS64 = np.finfo(np.float64).eps
+EPS32 = np.finfo(np.float32).eps
+
+
+def sine_mode(nx, ny, nz, p, q, r, h=1, dtype=np.float64):
+    u = np.zeros((nz + 2 * h, ny + 2 * h, nx + 2 * h))
+    i = np.arange(1, nx + 1)
+    j = np.arange(1, ny + 1)
+    k = np.arange(1, nz + 1)
+    sx = np.sin(np.pi * p * i / (nx + 1))
+    sy = np.sin(np.pi * q * j / (ny + 1))
+    sz = np.sin(np.pi * r * k / (nz + 1))
+    u[h:h + nz, h:h + ny, h:h + nx] = sz[:, None, None] * sy[None, :, None] * sx[None, None, :]
+    return u.astype(dtype)
+
+
+def mode_lambda(nx, ny, nz, p, q, r, a, b):
+    c = (math.cos(math.pi * p / (nx + 1)) + math.cos(math.pi * q / (ny + 1))
+         + math.cos(math.pi * r / (nz + 1)))
+    return a + 2.0 * b * c
+
+
+# --------------------------------------------------------------- Jacobi -----
+
+def pin_jacobi_sine_decay(lib):
+    """Closed form: each sweep multiplies the mode by lambda (FP64 and float)."""
+    cases = [((12, 10, 9), (1, 2, 3), 0.0, 1.0 / 6.0, 30),
+             ((9, 11, 7), (2, 1, 1), 0.25, 0.125, 30),
+             ((16, 5, 6), (3, 1, 2), 1.0 / 3.0, 1.0 / 9.0, 25)]
+    for (nx, ny, nz), (p, q, r), a, b, S in cases:
+        lam = mode_lambda(nx, ny, nz, p, q, r, a, b)
+        assert abs(lam) ** S >= 1e-3, "pick a mode that does not vanish"
+        u0 = sine_mode(nx, ny, nz, p, q, r)
+        out = oracle.jacobi(u0, S, a=a, b=b, lib=lib)
+        tol = 8 * S * EPS64 * np.abs(u0).max()
+        err = np.abs(out - (lam ** S) * u0).max()
+        assert err <= tol, (nx, ny, nz, p, q, r, a, b, err, tol)
+        out32 = oracle.jacobi(u0.astype(np.float32), S, a=a, b=b, lib=lib)
+        tol32 = 8 * S * EPS32 * np.abs(u0).max()
+        err32 = np.abs(out32.astype(np.float64) - (lam ** S) * u0).max()
+        assert err32 <= tol32, ("f32", nx, ny, nz, err32, tol32)
+
+
+def pin_fixed_points(lib):
+    """Constant and linear harmonic fields are exact fixed points (a + 6b = 1)."""
+    nx, ny, nz = 7, 6, 5
+    k, j, i = np.meshgrid(np.arange(nz + 2), np.arange(ny + 2), np.arange(nx + 2), indexing="ij")
+    fields = [np.full((nz + 2, ny + 2, nx + 2), 3.0),
+              (2 * i - 3 * j + 5 * k + 1).astype(np.float64),
+              (0.5 * i + 0.25 * j - 1.5 * k).astype(np.float64)]
+    for u in fields:
+        for a, b in ((0.25, 0.125), (0.5, 1.0 / 12.0 * 1.0)):
+            if a + 6 * b != 1.0:
+                continue
+            for fn in (oracle.jacobi, oracle.gauss_seidel):
+                out = fn(u, 6, a=a, b=b, lib=lib)
+                assert np.array_equal(out, u), (fn.__name__, a, b)
+                out32 = fn(u.astype(np.float32), 6, a=a, b=b, lib=lib)
+                assert np.array_equal(out32, u.astype(np.float32)), (fn.__name__, "f32")
+    # b = 1/6 is not dyadic: at most a couple of ulps per sweep.
+    u = np.full((nz + 2, ny + 2, nx + 2), 0.7)
+    for fn in (oracle.jacobi, oracle.gauss_seidel):
+        out = fn(u, 10, a=0.0, b=1.0 / 6.0, lib=lib)
+        assert np.abs(out - 0.7).max() <= 10 * 2 * EPS64, fn.__name__
+
+
+def _frac_sweeps(u, f, a, b, g, sweeps, in_place):
+    """Sec. 3 definitions in exact rational arithmetic (order-free)."""
+    nz, ny, nx = len(u) - 2, len(u[0]) - 2, len(u[0][0]) - 2
+    cur = [[[Fraction(v) for v in row] for row in plane] for plane in u]
+    for _ in range(sweeps):
+        src = cur
+        dst = cur if in_place else [[[v for v in row] for row in plane] for plane in cur]
+        for k in range(1, nz + 1):
+            for j in range(1, ny + 1):
+                for i in range(1, nx + 1):
+                    s = (src[k][j][i - 1] + src[k][j][i + 1] + src[k][j - 1][i]
+                         + src[k][j + 1][i] + src[k - 1][j][i] + src[k + 1][j][i])
+                    v = a * src[k][j][i] + b * s
+                    if f is not None:
+                        v += g * Fraction(f[k - 1][j - 1][i - 1])
+                    dst[k][j][i] = v
+        cur = dst
+    return cur
+
+
+def _check_frac(out, exact, mant_bits=53):
+    for k, plane in enumerate(exact):
+        for j, row in enumerate(plane):
+            for i, v in enumerate(row):
+                # the fixture is only meaningful while every value is representable
+                assert abs(v.numerator).bit_length() <= mant_bits, "fixture not exact"
+                assert Fraction(float(out[k, j, i])) == v, (k, j, i, float(out[k, j, i]), v)
+
+
+def pin_exact_rational(lib):
+    """Dyadic weights + integer data: FP64 result equals the exact rational one."""
+    rng = np.random.default_rng(1234)
+    nx, ny, nz = 4, 3, 5
+    u = rng.integers(-8, 9, size=(nz + 2, ny + 2, nx + 2)).astype(np.float64)
+    f = rng.integers(-4, 5, size=(nz, ny, nx)).astype(np.float64)
+    ul = u.tolist()
+    fl = f.tolist()
+    for a, b, g, use_f in ((Fraction(1, 4), Fraction(1, 8), Fraction(0), False),
+                           (Fraction(0), Fraction(1, 8), Fraction(1, 2), True),
+                           (Fraction(-1, 2), Fraction(1, 4), Fraction(3, 4), True)):
+        ff = f if use_f else None
+        for in_place, fn in ((False, oracle.jacobi), (True, oracle.gauss_seidel)):
+            exact = _frac_sweeps(ul, fl if use_f else None, a, b, g, 5, in_place)
+            out = fn(u, 5, a=float(a), b=float(b), f=ff, g=float(g), lib=lib)
+            _check_frac(out, exact)
+
+
+def pin_exact_rational_f32(lib):
+    """Same exact check for the float functions (values stay within 24 bits)."""
+    rng = np.random.default_rng(99)
+    a, b, g = Fraction(1, 4), Fraction(1, 8), Fraction(1, 2)
+    # Gauss-Seidel chains fresh values within a sweep, so its denominators grow
+    # with the grid diagonal: keep its grid and sweep count smaller.
+    for in_place, fn, (nx, ny, nz), S in ((False, oracle.jacobi, (3, 4, 3), 3),
+                                          (True, oracle.gauss_seidel, (3, 2, 2), 1)):
+        u = rng.integers(-4, 5, size=(nz + 2, ny + 2, nx + 2)).astype(np.float64)
+        f = rng.integers(-2, 3, size=(nz, ny, nx)).astype(np.float64)
+        exact = _frac_sweeps(u.tolist(), f.tolist(), a, b, g, S, in_place)
+        out = fn(u.astype(np.float32), S, a=0.25, b=0.125, f=f.astype(np.float32), g=0.5, lib=lib)
+        _check_frac(out.astype(np.float64), exact, mant_bits=24)
+
+
+# -------------------------------------------------------- Gauss-Seidel -----
+
+def pin_gs_rate(lib):
+    """Young: asymptotic GS factor = cos(pi/(n+1))^2; Jacobi's is cos(pi/(n+1))."""
+    n = 9
+    rng = np.random.default_rng(7)
+    u = np.zeros((n + 2, n + 2, n + 2))
+    u[1:-1, 1:-1, 1:-1] = rng.random((n, n, n))
+    rho_j = math.cos(math.pi / (n + 1))
+    for fn, expect in ((oracle.gauss_seidel, rho_j ** 2), (oracle.jacobi, rho_j)):
+        v = fn(u, 150 if fn is oracle.gauss_seidel else 300, lib=lib)
+        w = fn(v, 1, lib=lib)
+        ratio = np.linalg.norm(w) / np.linalg.norm(v)
+        assert abs(ratio - expect) < 2e-3, (fn.__name__, ratio, expect)
+
+
+def pin_gs_differs_from_jacobi(lib):
+    """One GS sweep must use fresh x-, y-, z- values: compare an impulse response."""
+    n = 5
+    u = np.zeros((n + 2, n + 2, n + 2))
+    u[1, 1, 1] = 6.0  # impulse at the first interior site
+    g = oracle.gauss_seidel(u, 1, a=0.0, b=1.0 / 8.0, lib=lib)
+    # Lexicographic order propagates the impulse to every later site with a
+    # monotone path; exact values: site (1,1,2) sees u(1,1,1)_new = 0 (it was
+    # overwritten by b*sum(0) = 0) -- so the impulse is erased before use.
+    assert g[1, 1, 1] == 0.0
+    assert np.count_nonzero(g) == 0
+    # Jacobi keeps the impulse for its neighbours.
+    j = oracle.jacobi(u, 1, a=0.0, b=1.0 / 8.0, lib=lib)
+    assert j[1, 1, 2] == 0.75 and j[1, 2, 1] == 0.75 and j[2, 1, 1] == 0.75
+    # an impulse at a central site: its three lower neighbours see the OLD
+    # value through +z/+y/+x (1 each), then the site itself sees those three
+    # FRESH values through -z/-y/-x (3/8); Jacobi gives 1 to all six
+    # neighbours and 0 to the site.
+    u = np.zeros((n + 2, n + 2, n + 2))
+    u[3, 3, 3] = 8.0
+    g = oracle.gauss_seidel(u, 1, a=0.0, b=1.0 / 8.0, lib=lib)
+    assert g[2, 3, 3] == 1.0 and g[3, 2, 3] == 1.0 and g[3, 3, 2] == 1.0
+    assert g[3, 3, 3] == 3.0 / 8.0
+    j = oracle.jacobi(u, 1, a=0.0, b=1.0 / 8.0, lib=lib)
+    assert j[3, 3, 3] == 0.0
+    for d in ((2, 3, 3), (4, 3, 3), (3, 2, 3), (3, 4, 3), (3, 3, 2), (3, 3, 4)):
+        assert j[d] == 1.0
+
+
+# ------------------------------------------------ residual, refinement -----
+
+def pin_residual_mode(lib):
+    """A u for the sine mode is (6 - 2 sum cos) u in closed form."""
+    nx, ny, nz = 10, 8, 6
+    u = sine_mode(nx, ny, nz, 2, 3, 1)
+    mu = 6.0 - 2.0 * (math.cos(2 * math.pi / (nx + 1)) + math.cos(3 * math.pi / (ny + 1))
+                      + math.cos(math.pi / (nz + 1)))
+    fp = 0.5 * np.ones((nz, ny, nx))
+    r, rr = oracle.residual(u, fp, lib=lib)
+    expect = fp - mu * u[1:-1, 1:-1, 1:-1]
+    assert np.abs(r - expect).max() <= 16 * EPS64
+    assert abs(rr - float(np.sum(expect * expect))) <= 1e-12 * rr
+
+
+def pin_defect_correction(lib):
+    """One outer step with m FP64 inner sweeps == m plain sweeps with f'."""
+    n = 10
+    rng = np.random.default_rng(5)
+    fp = (2 * rng.random((n, n, n)) - 1) / (n + 1) ** 2
+    u0 = np.zeros((n + 2, n + 2, n + 2))
+    u0[1:-1, 1:-1, 1:-1] = rng.random((n, n, n)) * 1e-3
+    for method in (0, 1):
+        m = 12
+        out, rc, outer, _ = oracle.refine(u0, fp, method=method, inner_f32=False, m=m,
+                                          tol=0.0, max_outer=1, lib=lib)
+        assert outer == 1 and rc == -6
+        plain = oracle.smooth(method, u0, m, a=0.0, b=1.0 / 6.0, f=fp, g=1.0 / 6.0, lib=lib)
+        scale = np.abs(plain).max()
+        assert np.abs(out - plain).max() <= 64 * m * EPS64 * scale, method
+        # float inner sweeps: equal up to float rounding of the correction
+        out32, _, _, _ = oracle.refine(u0, fp, method=method, inner_f32=True, m=m,
+                                       tol=0.0, max_outer=1, lib=lib)
+        assert np.abs(out32 - plain).max() <= 1e-5 * scale, method
+        # and the general one-step form used for serving jobs
+        job = oracle.refined_job(method, u0, m, a=0.0, b=1.0 / 6.0, f=fp, g=1.0 / 6.0, lib=lib)
+        assert np.abs(job - plain).max() <= 1e-5 * scale, method
+
+
+def pin_manufactured_solution(lib):
+    """The refinement loop converges to the known solution u* = sine(1,1,1)."""
+    n = 8
+    us = sine_mode(n, n, n, 1, 1, 1)
+    mu = 6.0 - 6.0 * math.cos(math.pi / (n + 1))
+    fp = mu * us[1:-1, 1:-1, 1:-1]
+    u0 = np.zeros_like(us)
+    for method in (0, 1):
+        for inner_f32 in (False, True):
+            out, rc, outer, rel = oracle.refine(u0, fp, method=method, inner_f32=inner_f32, m=16,
+                                                tol=1e-10, max_outer=400, lib=lib)
+            assert rc == 0 and rel <= 1e-10, (method, inner_f32, rc, rel)
+            # cond(A) ~ 12/mu < 30 bounds the error by 30 * 1e-10 relative
+            assert np.abs(out - us).max() <= 30 * 1e-10 * np.abs(us).max() + 1e-15
+    # GS needs about half the sweeps of Jacobi (rho_GS = rho_J^2)
+    _, _, oj, _ = oracle.refine(u0, fp + 1e-3, method=0, inner_f32=False, m=8, tol=1e-10,
+                                max_outer=2000, lib=lib)
+    _, _, og, _ = oracle.refine(u0, fp + 1e-3, method=1, inner_f32=False, m=8, tol=1e-10,
+                                max_outer=2000, lib=lib)
+    assert 0.4 <= og / oj <= 0.62, (oj, og)
+
+
+def pin_split_invariance(lib):
+    """S1 sweeps then S2 sweeps equal S1 + S2 sweeps (bit-exact)."""
+    rng = np.random.default_rng(3)
+    u = rng.random((8, 7, 9))
+    for fn in (oracle.jacobi, oracle.gauss_seidel):
+        once = fn(u, 7, lib=lib)
+        twice = fn(fn(u, 3, lib=lib), 4, lib=lib)
+        assert np.array_equal(once, twice), fn.__name__
+        assert np.array_equal(fn(u, 0, lib=lib), u)
+
+
+# ------------------------------------------------- printed loop nests -----
+
+def _listing_jacobi(u, S, a, b):
+    """Brute-force transcription of the Sec. 3 Jacobi loop nest (pure Python floats)."""
+    src = u.tolist()
+    nz, ny, nx = len(src) - 2, len(src[0]) - 2, len(src[0][0]) - 2
+    for _ in range(S):
+        dst = [[row[:] for row in plane] for plane in src]
+        for k in range(1, nz + 1):
+            for j in range(1, ny + 1):
+                for i in range(1, nx + 1):
+                    v = b * (src[k][j][i - 1] + src[k][j][i + 1] + src[k][j - 1][i]
+                             + src[k][j + 1][i] + src[k - 1][j][i] + src[k + 1][j][i])
+                    if a != 0.0:
+                        v = a * src[k][j][i] + v
+                    dst[k][j][i] = v
+        src = dst
+    return np.array(src)
+
+
+def _listing_gs(u, S, b):
+    """Brute-force transcription of the Sec. 3 Gauss-Seidel loop nest."""
+    src = u.tolist()
+    nz, ny, nx = len(src) - 2, len(src[0]) - 2, len(src[0][0]) - 2
+    for _ in range(S):
+        for k in range(1, nz + 1):
+            for j in range(1, ny + 1):
+                for i in range(1, nx + 1):
+                    src[k][j][i] = b * (src[k][j][i - 1] + src[k][j][i + 1] + src[k][j - 1][i]
+                                        + src[k][j + 1][i] + src[k - 1][j][i] + src[k + 1][j][i])
+    return np.array(src)
+
+
+def pin_listing_order(lib):
+    """Operand order of the printed loop nests (C left association), bit-exact."""
+    rng = np.random.default_rng(0)
+    u = np.zeros((10, 10, 10))
+    u[1:-1, 1:-1, 1:-1] = 2 * rng.random((8, 8, 8)) - 1
+    assert np.array_equal(oracle.gauss_seidel(u, 3, lib=lib), _listing_gs(u, 3, 1.0 / 6.0))
+    u = rng.random((7, 8, 9))
+    assert np.array_equal(oracle.jacobi(u, 4, lib=lib), _listing_jacobi(u, 4, 0.0, 1.0 / 6.0))
+    assert np.array_equal(oracle.jacobi(u, 2, a=0.3, b=0.1, lib=lib),
+                          _listing_jacobi(u, 2, 0.3, 0.1))
+
+
+ALL_PINS = [pin_listing_order, pin_jacobi_sine_decay, pin_fixed_points, pin_exact_rational, pin_exact_rational_f32,
+            pin_gs_rate, pin_gs_differs_from_jacobi, pin_residual_mode, pin_defect_correction,
+            pin_manufactured_solution, pin_split_invariance]
