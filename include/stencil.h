@@ -1,0 +1,271 @@
+/*
+ * stencil.h -- C ABI of libstencil, an MI355X (gfx950) library of iterated
+ * 3D 7-point smoothers: two-array Jacobi and in-place lexicographic
+ * Gauss-Seidel with several sweeps fused per pass over HBM, an FP64
+ * iterative-refinement solve around an FP32 inner smoother, and a
+ * continuous-batching job service.
+ *
+ * The methods are those of Treibig, Wellein, Hager, "Efficient
+ * multicore-aware parallelization strategies for iterative stencil
+ * computations" (Sec. 3 defines the Jacobi and Gauss-Seidel loop nests,
+ * Sec. 4 the temporal wavefront blocking; Eq. (1) the bandwidth model).
+ *
+ * ---------------------------------------------------------------------------
+ * Common conventions
+ *
+ *  Grid layout.  A grid has interior extents nx, ny, nz >= 1 and a ghost
+ *  layer of width halo >= 1 on every side.  It is one dense C array of
+ *  (nz+2*halo)*(ny+2*halo)*(nx+2*halo) elements, x contiguous:
+ *      index(k, j, i) = (k*(ny+2*halo) + j)*(nx+2*halo) + i,
+ *  interior i in [halo, halo+nx), likewise j, k.  Ghost cells hold Dirichlet
+ *  values; they are read (the innermost layer only) and never written by a
+ *  sweep.  A right-hand side f is interior-only: nz*ny*nx elements, x
+ *  contiguous.  The Sec. 3 listings read i-1 and i+1 at every interior site,
+ *  which implies this ghost layer.
+ *
+ *  Site update (Sec. 3 loop nests, with the Poisson right-hand side the
+ *  paper names; C left-to-right association of the printed sum):
+ *      s = ((((x- + x+) + y-) + y+) + z-) + z+
+ *      v = (center*c) + (neighbor*s)     -- center*c omitted when center == 0
+ *      v = v + (rhs*f)                   -- only when f != NULL
+ *  No fused multiply-add is used anywhere, so FP64 (and FP32) results are
+ *  bit-identical to a sequential CPU evaluation in the same order.  Jacobi
+ *  reads all operands from the previous sweep; Gauss-Seidel is in place in
+ *  lexicographic order (i fastest, then j, then k), so x-, y-, z- are new and
+ *  x+, y+, z+ are old.  Equal results are compared by value (+0 == -0).
+ *
+ *  dtype: ST_FP64 (double) or ST_FP32 (float storage and float arithmetic;
+ *  weights are rounded to float once).
+ *
+ *  Memory.  Every grid pointer is a device pointer (hipMalloc'd or a torch
+ *  device tensor).  The caller owns u, scratch and f; the library never frees
+ *  them and keeps no pointer after the stream work completes.  The library
+ *  owns only its internal flag/queue/workspace buffers.
+ *
+ *  Streams.  hip_stream is a hipStream_t (NULL = the default stream).
+ *  stencil_jacobi and stencil_gs only enqueue work and return; results are
+ *  ready when the stream reaches that point.
+ *
+ *  Errors.  Every function returns an st_status (0 or negative).  Argument
+ *  errors are detected before anything is enqueued.  A HIP launch failure is
+ *  ST_EHIP.  stencil_last_error() returns a thread-local message for the most
+ *  recent failure on the calling thread.  No C++ exception crosses the ABI.
+ * ---------------------------------------------------------------------------
+ */
+#ifndef STENCIL_H
+#define STENCIL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ST_OK = 0,
+    ST_EINVAL = -1,     /* invalid argument (dims, halo, dtype, pointer, t_fuse, ...) */
+    ST_ENOMEM = -2,     /* device or host allocation failed / budget too small */
+    ST_EHIP = -3,       /* a HIP runtime call or kernel launch failed */
+    ST_EBUSY = -4,      /* resource in use (e.g. service shutting down) */
+    ST_ENOENT = -5,     /* unknown job id */
+    ST_ENOCONV = -6,    /* refinement stopped at max_outer above rel_tol */
+    ST_ECANCELED = -7   /* job was cancelled */
+} st_status;
+
+typedef enum { ST_FP64 = 0, ST_FP32 = 1 } st_dtype;
+
+typedef enum { ST_BC_KEEP = 0, ST_BC_CONST = 1 } st_bc;
+
+/* Interior extents (>= 1) and ghost width (>= 1). */
+typedef struct {
+    int64_t nx, ny, nz;
+    int32_t halo;
+} st_grid;
+
+/* v = (center*c) + (neighbor*s) [+ rhs*f]; the paper's Jacobi uses
+ * center = a, neighbor = b; its Gauss-Seidel has center = 0. */
+typedef struct {
+    double center, neighbor, rhs;
+} st_weights;
+
+/*
+ * stencil_jacobi -- `sweeps` two-array Jacobi sweeps (Sec. 3 loop nest),
+ * fused `t` at a time per pass over HBM (Sec. 4 temporal wavefront blocking,
+ * re-expressed as a z-marching GPU tile that keeps the t time levels on chip).
+ *
+ *  u        in/out grid (dtype), result returned in u.
+ *  scratch  second grid of the same size (dtype); its contents on entry are
+ *           ignored and on return are unspecified.  Must not alias u.
+ *  f        interior-only right-hand side (dtype) or NULL.
+ *  w        weights (see above); w->rhs is ignored when f == NULL.
+ *  bc       ST_BC_KEEP: use u's ghost cells as given; ST_BC_CONST: first set
+ *           every ghost cell of u to bc_value.
+ *  sweeps   >= 0 (0 only applies bc).
+ *  t_fuse   sweeps fused per pass: 0 = automatic, or 1, 2, 4, 8, 16.  A pass
+ *           keeps at most 8 levels on chip; 16 runs as passes of 8.
+ *  Result: bit-identical to `sweeps` sequential sweeps for every t_fuse.
+ */
+int stencil_jacobi(const st_grid *grid, int32_t dtype, void *u, void *scratch, const void *f,
+                   const st_weights *w, int32_t bc, double bc_value, int32_t sweeps,
+                   int32_t t_fuse, void *hip_stream);
+
+/*
+ * stencil_jacobi_plan -- the pass schedule stencil_jacobi uses for
+ * (dtype, sweeps, t_fuse): writes the number of kernel launches to *passes,
+ * up to max_list per-pass fused-sweep counts to t_list (may be NULL), and
+ * whether a final scratch->u copy is needed to *final_copy (may be NULL).
+ */
+int stencil_jacobi_plan(int32_t dtype, int32_t sweeps, int32_t t_fuse, int32_t *passes,
+                        int32_t *t_list, int32_t max_list, int32_t *final_copy);
+
+/*
+ * stencil_gs -- `sweeps` in-place lexicographic Gauss-Seidel sweeps
+ * (Sec. 3 loop nest), run as a pipelined wavefront: the pipeline-parallel
+ * and temporal-wavefront schemes of Sec. 3/4 re-expressed as bundles of
+ * x-lines scheduled in topological order with per-bundle progress counters
+ * instead of barriers.  t_fuse sweeps are in flight per launch (0 = all
+ * sweeps in one launch; 1 = one launch per sweep).  Bit-identical to the
+ * sequential loop nest.  Uses an internal flag buffer owned by the library.
+ * Same argument meanings as stencil_jacobi.
+ */
+int stencil_gs(const st_grid *grid, int32_t dtype, void *u, const void *f, const st_weights *w,
+               int32_t bc, double bc_value, int32_t sweeps, int32_t t_fuse, void *hip_stream);
+
+/*
+ * stencil_residual -- FP64 residual of the h^2-scaled Poisson system
+ * A u = f' with A u = 6c - s (the a = 0, b = 1/6 smoother's operator):
+ *     r = f' - ((6*c) - s)
+ * u: FP64 grid; fp: interior-only FP64 right-hand side (NULL = zero);
+ * r_or_null: interior-only FP64 output or NULL; norm2_out (host pointer):
+ * sum of r^2, reduced in a fixed tree order (deterministic run to run).
+ * Synchronizes the stream before returning (*norm2_out is a host value).
+ */
+int stencil_residual(const st_grid *grid, const double *u, const double *fp, double *r_or_null,
+                     double *norm2_out, void *hip_stream);
+
+/*
+ * stencil_refine_solve -- solve A u = f' (above) to ||r||/||f'|| <= rel_tol.
+ *  inner_dtype ST_FP32 -- mixed-precision defect correction:
+ *      loop: r = f' - A u (FP64 on the GPU); stop when rel <= rel_tol;
+ *            e = inner_sweeps float sweeps of the method on A e = float(r)
+ *                from e = 0 with zero ghosts and weights (0, 1/6, 1/6)
+ *                (half the bytes per site of FP64);
+ *            u = u + double(e) (FP64).
+ *  inner_dtype ST_FP64 -- the plain FP64 method for comparison:
+ *      loop: r = f' - A u; stop when rel <= rel_tol;
+ *            u = inner_sweeps FP64 sweeps of the method on u itself with the
+ *                right-hand side f' and weights (0, 1/6, 1/6).
+ *  method      0 = Jacobi, 1 = Gauss-Seidel.
+ *  u           FP64 grid: initial guess in, solution out; ghosts = Dirichlet.
+ *  fp          interior-only FP64 right-hand side (h^2 f).
+ *  t_fuse      fused sweeps per pass of the inner smoother (0 = automatic).
+ *  max_outer   residual checks followed by smoothing allowed; ST_ENOCONV if
+ *              rel_tol is not reached after max_outer of them.
+ *  outer_done, rel_res_out  (host pointers, may be NULL): smoothing rounds
+ *              applied and the last relative residual.
+ * Allocates its workspace internally and frees it before returning.
+ * Synchronous.
+ */
+int stencil_refine_solve(const st_grid *grid, int32_t method, int32_t inner_dtype, double *u,
+                         const double *fp, int32_t inner_sweeps, int32_t t_fuse, double rel_tol,
+                         int32_t max_outer, int32_t *outer_done, double *rel_res_out,
+                         void *hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Continuous-batching job service.  Jobs (independent smoothing problems of
+ * uneven sizes) are submitted from host memory at any time; a scheduler
+ * thread admits them while the sum of their device footprints fits the HBM
+ * budget and fewer than max_inflight are resident, uploads them into a
+ * device pool, and runs every resident job's work inside shared persistent
+ * kernels; jobs admitted while others run join the next batch launch, so
+ * their work overlaps on the device.  A job's result does not depend on
+ * which other jobs ran with it.
+ */
+typedef struct smooth_ctx smooth_ctx;
+
+typedef struct {
+    uint64_t hbm_budget_bytes;  /* device pool size; jobs must fit inside it */
+    int32_t max_inflight;       /* resident jobs at most (>= 1) */
+    int32_t device;             /* HIP device ordinal */
+    int32_t t_fuse;             /* fused sweeps per Jacobi pass (0 = automatic) */
+    int32_t reserved;
+} smooth_config;
+
+enum { SMOOTH_JACOBI = 0, SMOOTH_GS = 1 };
+enum { SMOOTH_FP64 = 0, SMOOTH_FP32_REFINED = 1 };
+enum { SMOOTH_QUEUED = 0, SMOOTH_RUNNING = 1, SMOOTH_DONE = 2, SMOOTH_FAILED = 3,
+       SMOOTH_CANCELED = 4 };
+
+/*
+ * One smoothing job: `sweeps` sweeps of `method` on a grid of interior
+ * extents nx, ny, nz with a ghost layer of width 1.
+ *  precision SMOOTH_FP64: plain FP64 sweeps (bit-identical to stencil_jacobi
+ *            / stencil_gs).  SMOOTH_FP32_REFINED: one defect-correction step,
+ *            r = (one FP64 update of u0) - u0, `sweeps` float sweeps of
+ *            e <- (center*e) + (neighbor*s_e) + r from e = 0 with zero ghosts,
+ *            u = u0 + e in FP64 (equal to the plain result in exact
+ *            arithmetic; within float rounding of the correction in practice).
+ *  input_host  (nz+2)(ny+2)(nx+2) doubles, read during the call to
+ *              smooth_submit's admission (keep valid until DONE/FAILED/CANCELED).
+ *  output_host same size, written before the job turns DONE.
+ */
+typedef struct {
+    int64_t nx, ny, nz;
+    int32_t method;
+    int32_t precision;
+    int32_t sweeps;
+    int32_t reserved;
+    st_weights weights;
+    const double *input_host;
+    double *output_host;
+} smooth_job;
+
+/* Per-job timestamps (steady clock, ns) and accounting. */
+typedef struct {
+    int64_t t_submit_ns, t_admit_ns, t_start_ns, t_done_ns;
+    uint64_t footprint_bytes;   /* device bytes the job held while resident */
+    double lups;                /* lattice-site updates performed (interior sites * sweeps) */
+    int32_t batch_id;           /* launch batch that ran the job's sweeps */
+    int32_t reserved;
+} smooth_stats;
+
+/* Create a service: allocates the device pool (hbm_budget_bytes) and starts
+ * the scheduler thread.  ST_ENOMEM if the pool cannot be allocated. */
+int smooth_init(const smooth_config *cfg, smooth_ctx **out);
+
+/* Queue a job (non-blocking).  ST_EINVAL for bad extents/method/precision/
+ * sweeps or a footprint larger than the whole budget; *job_id receives an id
+ * unique within the context. */
+int smooth_submit(smooth_ctx *ctx, const smooth_job *job, uint64_t *job_id);
+
+/* Non-blocking state query; stats may be NULL.  ST_ENOENT for unknown ids. */
+int smooth_poll(smooth_ctx *ctx, uint64_t job_id, int32_t *state, smooth_stats *stats);
+
+/* Block until every submitted job is DONE, FAILED or CANCELED (timeout_ms < 0
+ * waits forever).  ST_EBUSY on timeout. */
+int smooth_wait_all(smooth_ctx *ctx, int64_t timeout_ms);
+
+/* Service-wide counters: pool high-water mark, batches launched, jobs done. */
+typedef struct {
+    uint64_t pool_bytes, footprint_high_water, footprint_now;
+    int64_t batches, jobs_done, jobs_failed, jobs_canceled;
+    int32_t max_resident_seen, reserved;
+} smooth_service_stats;
+int smooth_service_info(smooth_ctx *ctx, smooth_service_stats *out);
+
+/* Cancel queued jobs (CANCELED), let resident jobs finish, stop the thread,
+ * free the pool and the context. */
+int smooth_shutdown(smooth_ctx *ctx);
+
+/* Human-readable name of a status code, and the calling thread's last error. */
+const char *stencil_strerror(int status);
+const char *stencil_last_error(void);
+
+/* Library version string. */
+const char *stencil_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STENCIL_H */

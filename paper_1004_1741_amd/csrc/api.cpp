@@ -1,0 +1,340 @@
+// api.cpp -- the C ABI of libstencil (include/stencil.h): argument checks,
+// the Jacobi pass schedule, and the refinement loop.  All numerical work is
+// done by the HIP kernels in jacobi.hip, gs.hip and aux.hip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/stencil.h"
+#include "internal.h"
+
+namespace stk {
+
+static thread_local std::string t_last_error;
+
+void set_error(const std::string &msg) { t_last_error = msg; }
+
+}  // namespace stk
+
+using namespace stk;
+
+namespace {
+
+int fail(int status, const std::string &msg) {
+    set_error(msg);
+    return status;
+}
+
+int hip_fail(hipError_t e, const char *where) {
+    return fail(ST_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, where)                      \
+    do {                                          \
+        hipError_t e_ = (expr);                   \
+        if (e_ != hipSuccess) return hip_fail(e_, where); \
+    } while (0)
+
+int check_grid(const st_grid *g, Geom *out) {
+    if (!g) return fail(ST_EINVAL, "grid is NULL");
+    if (g->nx < 1 || g->ny < 1 || g->nz < 1)
+        return fail(ST_EINVAL, "interior extents must be >= 1");
+    if (g->halo < 1) return fail(ST_EINVAL, "halo must be >= 1");
+    const int64_t px = g->nx + 2 * (int64_t)g->halo, py = g->ny + 2 * (int64_t)g->halo,
+                  pz = g->nz + 2 * (int64_t)g->halo;
+    // kernels index within a plane with 32-bit arithmetic
+    if (px * py >= (int64_t)1 << 31 || pz >= (int64_t)1 << 31 || g->halo > 4096)
+        return fail(ST_EINVAL, "grid too large (one padded plane must hold < 2^31 elements)");
+    out->nx = (int)g->nx;
+    out->ny = (int)g->ny;
+    out->nz = (int)g->nz;
+    out->h = g->halo;
+    out->px = px;
+    out->py = py;
+    out->pz = pz;
+    return ST_OK;
+}
+
+bool valid_t(int t) { return t == 0 || t == 1 || t == 2 || t == 4 || t == 8 || t == 16; }
+
+int auto_t(int dtype) { return dtype == ST_FP32 ? 8 : 4; }
+
+// Pass schedule: floor(S/t) passes of t plus the binary decomposition of the
+// remainder; if the count is odd the smallest pass with >= 2 sweeps is split
+// in two so the result lands in u, else a final copy is needed.
+std::vector<int> jacobi_plan(int dtype, int sweeps, int t_fuse, bool *final_copy) {
+    int t = t_fuse == 0 ? auto_t(dtype) : t_fuse;
+    if (t > 8) t = 8;  // at most 8 levels fit on chip per pass
+    std::vector<int> p;
+    for (int i = 0; i < sweeps / t; ++i) p.push_back(t);
+    int rem = sweeps % t;
+    for (int b = 8; b >= 1; b >>= 1)
+        if (rem & b) p.push_back(b);
+    *final_copy = false;
+    if (p.size() % 2 == 1) {
+        int best = -1;
+        for (size_t i = 0; i < p.size(); ++i)
+            if (p[i] >= 2 && (best < 0 || p[i] < p[best])) best = (int)i;
+        if (best >= 0) {
+            const int half = p[best] / 2;
+            p[best] = half;
+            p.insert(p.begin() + best + 1, half);
+        } else {
+            *final_copy = true;
+        }
+    }
+    return p;
+}
+
+bool overlaps(const void *a, const void *b, size_t bytes) {
+    const char *x = (const char *)a, *y = (const char *)b;
+    return x < y + bytes && y < x + bytes;
+}
+
+int run_jacobi(const Geom &g, bool fp32, void *u, void *scratch, const void *f, double a,
+               double b, double gw, int sweeps, int t_fuse, hipStream_t s) {
+    if (sweeps == 0) return ST_OK;
+    bool fc = false;
+    std::vector<int> plan = jacobi_plan(fp32 ? ST_FP32 : ST_FP64, sweeps, t_fuse, &fc);
+    HIP_TRY(launch_copy_ghosts(fp32, g, u, scratch, s), "ghost copy");
+    const void *src = u;
+    void *dst = scratch;
+    for (int tb : plan) {
+        HIP_TRY(launch_jacobi_pass(fp32, tb, g, src, dst, f, a, b, gw, 0, s), "jacobi pass");
+        void *t = const_cast<void *>(src);
+        src = dst;
+        dst = t;
+    }
+    if (fc) HIP_TRY(launch_copy_interior(fp32, g, scratch, u, s), "final copy");
+    return ST_OK;
+}
+
+int run_gs(const Geom &g, bool fp32, void *u, const void *f, double a, double b, double gw,
+           int sweeps, int t_fuse, hipStream_t s) {
+    int per = t_fuse == 0 ? 4095 : t_fuse;
+    if (per > 4095) per = 4095;
+    for (int done = 0; done < sweeps; done += per) {
+        const int n = sweeps - done < per ? sweeps - done : per;
+        std::string err;
+        hipError_t e = launch_gs(fp32, g, u, f, a, b, gw, n, s, &err);
+        if (e != hipSuccess)
+            return err.empty() ? hip_fail(e, "gauss-seidel launch") : fail(ST_EINVAL, err);
+    }
+    return ST_OK;
+}
+
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+    hipError_t alloc(size_t bytes) { return hipMalloc(&p, bytes ? bytes : 1); }
+};
+
+}  // namespace
+
+extern "C" {
+
+const char *stencil_version(void) { return "libstencil 0.1 (gfx950)"; }
+
+const char *stencil_strerror(int status) {
+    switch (status) {
+        case ST_OK: return "ok";
+        case ST_EINVAL: return "invalid argument";
+        case ST_ENOMEM: return "out of memory";
+        case ST_EHIP: return "HIP runtime error";
+        case ST_EBUSY: return "busy";
+        case ST_ENOENT: return "no such job";
+        case ST_ENOCONV: return "not converged";
+        case ST_ECANCELED: return "canceled";
+        default: return "unknown status";
+    }
+}
+
+const char *stencil_last_error(void) { return t_last_error.c_str(); }
+
+int stencil_jacobi_plan(int32_t dtype, int32_t sweeps, int32_t t_fuse, int32_t *passes,
+                        int32_t *t_list, int32_t max_list, int32_t *final_copy) {
+    if (dtype != ST_FP64 && dtype != ST_FP32) return fail(ST_EINVAL, "dtype must be FP64 or FP32");
+    if (sweeps < 0) return fail(ST_EINVAL, "sweeps must be >= 0");
+    if (!valid_t(t_fuse)) return fail(ST_EINVAL, "t_fuse must be 0, 1, 2, 4, 8 or 16");
+    if (!passes) return fail(ST_EINVAL, "passes is NULL");
+    bool fc = false;
+    std::vector<int> p = sweeps ? jacobi_plan(dtype, sweeps, t_fuse, &fc) : std::vector<int>();
+    *passes = (int32_t)p.size();
+    if (t_list)
+        for (int i = 0; i < (int)p.size() && i < max_list; ++i) t_list[i] = p[i];
+    if (final_copy) *final_copy = fc ? 1 : 0;
+    return ST_OK;
+}
+
+int stencil_jacobi(const st_grid *grid, int32_t dtype, void *u, void *scratch, const void *f,
+                   const st_weights *w, int32_t bc, double bc_value, int32_t sweeps,
+                   int32_t t_fuse, void *hip_stream) {
+    Geom g;
+    int rc = check_grid(grid, &g);
+    if (rc) return rc;
+    if (dtype != ST_FP64 && dtype != ST_FP32) return fail(ST_EINVAL, "dtype must be FP64 or FP32");
+    if (!u || !scratch) return fail(ST_EINVAL, "u and scratch must be device pointers");
+    if (!w) return fail(ST_EINVAL, "weights is NULL");
+    if (bc != ST_BC_KEEP && bc != ST_BC_CONST) return fail(ST_EINVAL, "bc must be KEEP or CONST");
+    if (sweeps < 0) return fail(ST_EINVAL, "sweeps must be >= 0");
+    if (!valid_t(t_fuse)) return fail(ST_EINVAL, "t_fuse must be 0, 1, 2, 4, 8 or 16");
+    const bool fp32 = dtype == ST_FP32;
+    const size_t bytes = (size_t)g.count() * (fp32 ? 4 : 8);
+    if (overlaps(u, scratch, bytes)) return fail(ST_EINVAL, "u and scratch overlap");
+    if (!std::isfinite(w->center) || !std::isfinite(w->neighbor) || !std::isfinite(w->rhs))
+        return fail(ST_EINVAL, "weights must be finite");
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (bc == ST_BC_CONST) HIP_TRY(launch_fill_ghosts(fp32, g, u, bc_value, s), "ghost fill");
+    return run_jacobi(g, fp32, u, scratch, f, w->center, w->neighbor, f ? w->rhs : 0.0, sweeps,
+                      t_fuse, s);
+}
+
+int stencil_gs(const st_grid *grid, int32_t dtype, void *u, const void *f, const st_weights *w,
+               int32_t bc, double bc_value, int32_t sweeps, int32_t t_fuse, void *hip_stream) {
+    Geom g;
+    int rc = check_grid(grid, &g);
+    if (rc) return rc;
+    if (dtype != ST_FP64 && dtype != ST_FP32) return fail(ST_EINVAL, "dtype must be FP64 or FP32");
+    if (!u) return fail(ST_EINVAL, "u must be a device pointer");
+    if (!w) return fail(ST_EINVAL, "weights is NULL");
+    if (bc != ST_BC_KEEP && bc != ST_BC_CONST) return fail(ST_EINVAL, "bc must be KEEP or CONST");
+    if (sweeps < 0) return fail(ST_EINVAL, "sweeps must be >= 0");
+    if (!valid_t(t_fuse)) return fail(ST_EINVAL, "t_fuse must be 0, 1, 2, 4, 8 or 16");
+    if (g.ny > 8192 || g.nz > 8192)
+        return fail(ST_EINVAL, "Gauss-Seidel supports ny, nz <= 8192");
+    if (!std::isfinite(w->center) || !std::isfinite(w->neighbor) || !std::isfinite(w->rhs))
+        return fail(ST_EINVAL, "weights must be finite");
+    const bool fp32 = dtype == ST_FP32;
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (bc == ST_BC_CONST) HIP_TRY(launch_fill_ghosts(fp32, g, u, bc_value, s), "ghost fill");
+    if (sweeps == 0) return ST_OK;
+    return run_gs(g, fp32, u, f, w->center, w->neighbor, f ? w->rhs : 0.0, sweeps, t_fuse, s);
+}
+
+int stencil_residual(const st_grid *grid, const double *u, const double *fp, double *r_or_null,
+                     double *norm2_out, void *hip_stream) {
+    Geom g;
+    int rc = check_grid(grid, &g);
+    if (rc) return rc;
+    if (!u) return fail(ST_EINVAL, "u must be a device pointer");
+    if (!norm2_out) return fail(ST_EINVAL, "norm2_out is NULL");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int nb = residual_partial_count(g);
+    DevBuf part;
+    HIP_TRY(part.alloc(((size_t)nb + 1) * sizeof(double)), "residual workspace");
+    double *partials = (double *)part.p;
+    HIP_TRY(launch_residual_poisson(g, u, fp, r_or_null, nullptr, partials, nullptr, s),
+            "residual");
+    HIP_TRY(launch_sum_partials(partials, nb, partials + nb, s), "residual sum");
+    double host = 0.0;
+    HIP_TRY(hipMemcpyAsync(&host, partials + nb, sizeof(double), hipMemcpyDeviceToHost, s),
+            "residual copy");
+    HIP_TRY(hipStreamSynchronize(s), "residual sync");
+    *norm2_out = host;
+    return ST_OK;
+}
+
+int stencil_refine_solve(const st_grid *grid, int32_t method, int32_t inner_dtype, double *u,
+                         const double *fp, int32_t inner_sweeps, int32_t t_fuse, double rel_tol,
+                         int32_t max_outer, int32_t *outer_done, double *rel_res_out,
+                         void *hip_stream) {
+    Geom g;
+    int rc = check_grid(grid, &g);
+    if (rc) return rc;
+    if (method != 0 && method != 1) return fail(ST_EINVAL, "method must be 0 (Jacobi) or 1 (GS)");
+    if (inner_dtype != ST_FP64 && inner_dtype != ST_FP32)
+        return fail(ST_EINVAL, "inner_dtype must be FP64 or FP32");
+    if (!u || !fp) return fail(ST_EINVAL, "u and fp must be device pointers");
+    if (inner_sweeps < 1) return fail(ST_EINVAL, "inner_sweeps must be >= 1");
+    if (max_outer < 0) return fail(ST_EINVAL, "max_outer must be >= 0");
+    if (!valid_t(t_fuse)) return fail(ST_EINVAL, "t_fuse must be 0, 1, 2, 4, 8 or 16");
+    if (!(rel_tol >= 0.0)) return fail(ST_EINVAL, "rel_tol must be >= 0");
+    if (method == 1 && (g.ny > 8192 || g.nz > 8192))
+        return fail(ST_EINVAL, "Gauss-Seidel supports ny, nz <= 8192");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const bool f32 = inner_dtype == ST_FP32;
+    const int64_t ni = g.interior(), np = g.count();
+    const int nb = residual_partial_count(g);
+
+    DevBuf part, rbuf, ebuf, sbuf;
+    HIP_TRY(part.alloc(((size_t)nb + 2) * sizeof(double)), "refine workspace");
+    double *partials = (double *)part.p;
+    double *dsum = partials + nb;
+    if (f32) {
+        HIP_TRY(rbuf.alloc((size_t)ni * sizeof(float)), "refine workspace");
+        HIP_TRY(ebuf.alloc((size_t)np * sizeof(float)), "refine workspace");
+        if (method == 0) HIP_TRY(sbuf.alloc((size_t)np * sizeof(float)), "refine workspace");
+    } else if (method == 0) {
+        HIP_TRY(sbuf.alloc((size_t)np * sizeof(double)), "refine workspace");
+    }
+    // ||f'|| with the same deterministic reduction (residual of u = 0 is f')
+    {
+        DevBuf zero;
+        HIP_TRY(zero.alloc((size_t)np * sizeof(double)), "refine workspace");
+        HIP_TRY(hipMemsetAsync(zero.p, 0, (size_t)np * sizeof(double), s), "memset");
+        HIP_TRY(launch_residual_poisson(g, (const double *)zero.p, fp, nullptr, nullptr, partials,
+                                        nullptr, s), "norm f");
+        HIP_TRY(launch_sum_partials(partials, nb, dsum + 1, s), "norm f");
+        HIP_TRY(hipStreamSynchronize(s), "sync");
+    }
+    double ff = 0.0;
+    HIP_TRY(hipMemcpy(&ff, dsum + 1, sizeof(double), hipMemcpyDeviceToHost), "copy");
+    const double nf = std::sqrt(ff);
+    if (f32) {
+        HIP_TRY(hipMemsetAsync(ebuf.p, 0, (size_t)np * sizeof(float), s), "memset");
+        if (sbuf.p) HIP_TRY(hipMemsetAsync(sbuf.p, 0, (size_t)np * sizeof(float), s), "memset");
+    }
+    const st_weights pw = {0.0, 1.0 / 6.0, 1.0 / 6.0};
+    int outer = 0;
+    double rel = INFINITY;
+    int status = ST_ENOCONV;
+    for (;;) {
+        HIP_TRY(launch_residual_poisson(g, u, fp, nullptr, f32 ? (float *)rbuf.p : nullptr,
+                                        partials, nullptr, s), "residual");
+        HIP_TRY(launch_sum_partials(partials, nb, dsum, s), "residual sum");
+        double rr = 0.0;
+        HIP_TRY(hipMemcpyAsync(&rr, dsum, sizeof(double), hipMemcpyDeviceToHost, s), "copy");
+        HIP_TRY(hipStreamSynchronize(s), "sync");
+        rel = nf > 0.0 ? std::sqrt(rr) / nf : std::sqrt(rr);
+        if (rel <= rel_tol) {
+            status = ST_OK;
+            break;
+        }
+        if (outer >= max_outer) break;
+        if (f32) {
+            // e = 0 (ghosts stay 0), then inner_sweeps float sweeps on A e = r
+            HIP_TRY(hipMemsetAsync(ebuf.p, 0, (size_t)np * sizeof(float), s), "memset");
+            if (method == 0)
+                rc = run_jacobi(g, true, ebuf.p, sbuf.p, rbuf.p, pw.center, pw.neighbor, pw.rhs,
+                                inner_sweeps, t_fuse, s);
+            else
+                rc = run_gs(g, true, ebuf.p, rbuf.p, pw.center, pw.neighbor, pw.rhs,
+                            inner_sweeps, t_fuse, s);
+            if (rc) return rc;
+            HIP_TRY(launch_correct(g, u, ebuf.p, true, s), "correct");
+        } else {
+            // the plain FP64 method: smooth u itself with the right-hand side
+            if (method == 0)
+                rc = run_jacobi(g, false, u, sbuf.p, fp, pw.center, pw.neighbor, pw.rhs,
+                                inner_sweeps, t_fuse, s);
+            else
+                rc = run_gs(g, false, u, fp, pw.center, pw.neighbor, pw.rhs, inner_sweeps,
+                            t_fuse, s);
+            if (rc) return rc;
+        }
+        ++outer;
+    }
+    HIP_TRY(hipStreamSynchronize(s), "sync");
+    if (outer_done) *outer_done = outer;
+    if (rel_res_out) *rel_res_out = rel;
+    if (status == ST_ENOCONV) set_error("relative residual above rel_tol after max_outer steps");
+    return status;
+}
+
+}  // extern "C"

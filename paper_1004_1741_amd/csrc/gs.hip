@@ -1,0 +1,362 @@
+// gs.hip -- in-place lexicographic Gauss-Seidel as a pipelined wavefront.
+//
+// Method (Sec. 3 Gauss-Seidel loop nest; Sec. 3 pipeline-parallel scheme and
+// Sec. 4 temporal wavefront GS).  A site's update reads fresh x-, y-, z-
+// values of the current sweep and old x+, y+, z+ values of the previous one.
+// Because the 7-point stencil only couples axis neighbours, the result only
+// depends on that fresh/old split, so any schedule that runs site (i,j,k) of
+// sweep tau after (i-1,j,k), (i,j-1,k), (i,j,k-1) of sweep tau and after
+// (i+1,j,k), (i,j+1,k), (i,j,k+1) of sweep tau-1 reproduces the sequential
+// loop bit for bit.  The paper keeps the order by giving each thread of a
+// pipeline a sub-block, shifted in time; here:
+//
+//   * the (j,k) cross-section is cut into bundles of 8x8 x-lines; one wave
+//     owns a bundle for one sweep (a work item) and marches along x.  Lane
+//     (jj,kk) handles line (j0+jj, k0+kk) and at step T updates position
+//     i = T - jj - kk: its fresh y-/z- neighbours were written by lanes
+//     (jj-1,kk)/(jj,kk-1) one step earlier, its old y+/z+ neighbours are not
+//     yet overwritten by (jj+1,kk)/(jj,kk+1);
+//   * the bundle's lines and the four neighbour lines around it are staged in
+//     an LDS ring of 32 x positions, loaded and stored in coalesced chunks of
+//     8 positions;
+//   * items (tau, J, K) are handed out by an atomic ticket in order of
+//     2*tau + J + K, a topological order of their dependencies, so a wave only
+//     ever waits on items already held by running waves (no deadlock, no
+//     co-residency requirement).  Instead of barriers, a wave publishes a
+//     monotone progress counter per bundle after storing each chunk and polls
+//     its neighbours' counters before loading one (acquire/release at agent
+//     scope, across XCDs);
+//   * all sweeps of a launch are in flight at once: sweep tau+1 of a bundle
+//     trails sweep tau by a few chunks, so the intermediate sweeps of a band
+//     of the grid are re-read from L2/MALL instead of HBM.
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "internal.h"
+
+#pragma clang fp contract(off)
+
+namespace stk {
+namespace {
+
+constexpr int GS_C = 8;       // positions per load/store chunk
+constexpr int GS_RING = 32;   // ring positions per staged line (4 chunks)
+constexpr int GS_S = 41;      // LDS stride per line: S = 9 (mod 16) makes the
+                              // 64 lanes' reads hit distinct banks
+constexpr int GS_SLOTS = 100; // 10 x 10 staged lines (corners unused)
+
+template <typename T>
+struct GsArgs {
+    T *u;
+    const T *f;
+    int64_t px, plane;
+    int nx, ny, nz, h;
+    T a, b, g;
+    int nj, nk;          // bundles in y and z
+    int ncs;             // store chunks per line
+    int ncl;             // load chunks per line (includes the x+ ghost)
+    int nb;              // step blocks
+    uint32_t nitems;
+    const uint32_t *items;   // (tau << 20) | (J << 10) | K, topologically ordered
+    uint32_t *progress;      // per bundle, monotone
+    uint32_t *ticket;
+};
+
+__device__ __forceinline__ uint32_t done_mark(int tau, int c, int ncs) {
+    return (uint32_t)tau * (uint32_t)(ncs + 1) + (uint32_t)c + 1u;
+}
+
+__device__ __forceinline__ void wait_at_least(const uint32_t *p, uint32_t need) {
+    while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need)
+        __builtin_amdgcn_s_sleep(2);
+}
+
+// slot index (10x10 grid, jl fastest) of the li-th non-corner staged line
+__device__ __forceinline__ int staged_slot(int li) {
+    if (li < 8) return li + 1;                       // kl = 0, jl = 1..8
+    if (li < 88) return 10 + (li - 8);               // kl = 1..8, jl = 0..9
+    return 90 + (li - 88) + 1;                       // kl = 9, jl = 1..8
+}
+
+template <typename T, bool HAS_A, bool HAS_F>
+__global__ void __launch_bounds__(64) gs_wavefront_kernel(GsArgs<T> A) {
+    __shared__ T ring[GS_SLOTS * GS_S];
+    __shared__ T fring[HAS_F ? 78 * GS_S : 1];
+    const int lane = threadIdx.x;
+    const int kk = lane & 7, jj = lane >> 3;  // kk fastest: conflict-free LDS
+    const int d = jj + kk;                    // skew of this lane's line
+    const int own = (kk + 1) * 10 + (jj + 1);
+    const int fown = kk * 10 + jj;
+    const int h = A.h;
+
+    for (;;) {
+        uint32_t t = 0;
+        if (lane == 0)
+            t = __hip_atomic_fetch_add(A.ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        t = __shfl(t, 0, 64);
+        if (t >= A.nitems) break;
+        const uint32_t it = A.items[t];
+        const int tau = (int)(it >> 20);
+        const int J = (int)((it >> 10) & 1023u);
+        const int K = (int)(it & 1023u);
+        const int j0 = h + 8 * J, k0 = h + 8 * K;
+        const int j = j0 + jj, k = k0 + kk;
+        const bool active = (j < h + A.ny) && (k < h + A.nz);
+        uint32_t *P = A.progress;
+        const int me = K * A.nj + J;
+
+        auto wait_chunk = [&](int c) {
+            if (c * GS_C >= A.nx) return;  // only the x+ ghost column: never written
+            if (tau > 0) {
+                const uint32_t need = done_mark(tau - 1, c, A.ncs);
+                wait_at_least(P + me, need);
+                if (J + 1 < A.nj) wait_at_least(P + me + 1, need);
+                if (K + 1 < A.nk) wait_at_least(P + me + A.nj, need);
+            }
+            const uint32_t need_new = done_mark(tau, c, A.ncs);
+            if (J > 0) wait_at_least(P + me - 1, need_new);
+            if (K > 0) wait_at_least(P + me - A.nj, need_new);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        };
+        auto load_chunk = [&](int c) {
+#pragma unroll
+            for (int m = 0; m < 12; ++m) {
+                const int e = lane + 64 * m;
+                const int li = e >> 3;
+                const int i = c * GS_C + (e & 7);
+                const int slot = staged_slot(li);
+                const int jl = slot % 10, kl = slot / 10;
+                const int jg = j0 - 1 + jl, kg = k0 - 1 + kl;
+                const bool ok = i <= A.nx && jg <= h + A.ny && kg <= h + A.nz;
+                T v = T(0);
+                if (ok) v = A.u[(int64_t)kg * A.plane + (int64_t)jg * A.px + h + i];
+                ring[slot * GS_S + (i & (GS_RING - 1))] = v;
+            }
+            if constexpr (HAS_F) {
+#pragma unroll
+                for (int m = 0; m < 8; ++m) {
+                    const int e = lane + 64 * m;
+                    const int li = e >> 3;  // own line li = jj' + 8*kk'
+                    const int i = c * GS_C + (e & 7);
+                    const int jq = li & 7, kq = li >> 3;
+                    const int jg = j0 + jq, kg = k0 + kq;
+                    T v = T(0);
+                    if (i < A.nx && jg < h + A.ny && kg < h + A.nz)
+                        v = A.f[((int64_t)(kg - h) * A.ny + (jg - h)) * A.nx + i];
+                    fring[(kq * 10 + jq) * GS_S + (i & (GS_RING - 1))] = v;
+                }
+            }
+        };
+        auto store_chunk = [&](int c) {
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                const int e = lane + 64 * m;
+                const int li = e >> 3;
+                const int i = c * GS_C + (e & 7);
+                const int jq = li & 7, kq = li >> 3;
+                const int jg = j0 + jq, kg = k0 + kq;
+                if (i < A.nx && jg < h + A.ny && kg < h + A.nz)
+                    A.u[(int64_t)kg * A.plane + (int64_t)jg * A.px + h + i] =
+                        ring[((kq + 1) * 10 + (jq + 1)) * GS_S + (i & (GS_RING - 1))];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            if (lane == 0)
+                __hip_atomic_store(P + me, done_mark(tau, c, A.ncs), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        };
+
+        // x- ghost of this lane's line
+        T xm = T(0);
+        if (active) xm = A.u[(int64_t)k * A.plane + (int64_t)j * A.px + (h - 1)];
+
+        wait_chunk(0);
+        load_chunk(0);
+        if (A.ncl > 1) {
+            wait_chunk(1);
+            load_chunk(1);
+        }
+        for (int b = 0; b < A.nb; ++b) {
+#pragma unroll
+            for (int st = 0; st < GS_C; ++st) {
+                const int i = b * GS_C + st - d;
+                if (active && i >= 0 && i < A.nx) {
+                    const int p = i & (GS_RING - 1);
+                    const T xp = ring[own * GS_S + ((i + 1) & (GS_RING - 1))];
+                    const T ym = ring[(own - 1) * GS_S + p];
+                    const T yp = ring[(own + 1) * GS_S + p];
+                    const T zm = ring[(own - 10) * GS_S + p];
+                    const T zp = ring[(own + 10) * GS_S + p];
+                    T s = xm + xp;
+                    s = s + ym;
+                    s = s + yp;
+                    s = s + zm;
+                    s = s + zp;
+                    T v;
+                    if constexpr (HAS_A)
+                        v = (A.a * ring[own * GS_S + p]) + (A.b * s);
+                    else
+                        v = A.b * s;
+                    if constexpr (HAS_F) v = v + (A.g * fring[fown * GS_S + p]);
+                    ring[own * GS_S + p] = v;
+                    xm = v;
+                }
+                // LDS traffic of one wave is processed in order; keep the
+                // compiler from moving this step's write after the next reads
+                __builtin_amdgcn_wave_barrier();
+            }
+            const int cs = b - 2;  // the trailing lane (skew 14) has finished it
+            if (cs >= 0 && cs < A.ncs) store_chunk(cs);
+            const int cl = b + 2;
+            if (cl < A.ncl) {
+                wait_chunk(cl);
+                load_chunk(cl);
+            }
+        }
+        for (int cs = max(0, A.nb - 2); cs < A.ncs; ++cs) store_chunk(cs);
+    }
+}
+
+__global__ void gs_reset_kernel(uint32_t *progress, int n, uint32_t *ticket) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        progress[i] = 0u;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *ticket = 0u;
+}
+
+// ---- host side: item tables and flag buffers (library-owned) ----
+
+struct GsBuffers {
+    uint32_t *progress = nullptr;
+    uint32_t *ticket = nullptr;
+    int cap = 0;
+};
+
+std::mutex g_gs_mu;
+// Progress counters and the ticket are reset at the start of every launch, so
+// launches that may run concurrently (different streams) get separate ones;
+// launches on one stream are ordered and can share them.
+std::map<std::pair<int, hipStream_t>, GsBuffers> g_gs_bufs;
+std::map<std::tuple<int, int, int, int>, uint32_t *> g_gs_items;  // (dev, nj, nk, S)
+
+hipError_t get_items(int dev, int nj, int nk, int S, uint32_t **out, uint32_t *count) {
+    auto key = std::make_tuple(dev, nj, nk, S);
+    *count = (uint32_t)S * nj * nk;
+    auto itx = g_gs_items.find(key);
+    if (itx != g_gs_items.end()) {
+        *out = itx->second;
+        return hipSuccess;
+    }
+    std::vector<uint32_t> items;
+    items.reserve(*count);
+    const int kmax = 2 * (S - 1) + (nj - 1) + (nk - 1);
+    for (int key2 = 0; key2 <= kmax; ++key2)
+        for (int tau = 0; tau < S; ++tau) {
+            const int rest = key2 - 2 * tau;
+            if (rest < 0) break;
+            for (int J = 0; J < nj; ++J) {
+                const int K = rest - J;
+                if (K < 0) break;
+                if (K >= nk) continue;
+                items.push_back(((uint32_t)tau << 20) | ((uint32_t)J << 10) | (uint32_t)K);
+            }
+        }
+    uint32_t *d = nullptr;
+    hipError_t e = hipMalloc(&d, items.size() * sizeof(uint32_t));
+    if (e != hipSuccess) return e;
+    e = hipMemcpy(d, items.data(), items.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return e;
+    }
+    g_gs_items[key] = d;
+    *out = d;
+    return hipSuccess;
+}
+
+hipError_t get_bufs(int dev, hipStream_t s, int nbundles, GsBuffers **out) {
+    GsBuffers &B = g_gs_bufs[std::make_pair(dev, s)];
+    if (B.cap < nbundles) {
+        if (B.progress) (void)hipFree(B.progress);
+        if (B.ticket) (void)hipFree(B.ticket);
+        B.progress = nullptr;
+        B.ticket = nullptr;
+        B.cap = 0;
+        hipError_t e = hipMalloc(&B.progress, (size_t)nbundles * sizeof(uint32_t));
+        if (e != hipSuccess) return e;
+        e = hipMalloc(&B.ticket, 256);
+        if (e != hipSuccess) return e;
+        B.cap = nbundles;
+    }
+    *out = &B;
+    return hipSuccess;
+}
+
+template <typename T, bool HAS_A, bool HAS_F>
+hipError_t launch_gs_t(const Geom &g, void *u, const void *f, double a, double b, double gw,
+                       int S, hipStream_t s, std::string *err) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    GsArgs<T> A;
+    A.u = static_cast<T *>(u);
+    A.f = static_cast<const T *>(f);
+    A.px = g.px;
+    A.plane = g.plane();
+    A.nx = g.nx; A.ny = g.ny; A.nz = g.nz; A.h = g.h;
+    A.a = (T)a; A.b = (T)b; A.g = (T)gw;
+    A.nj = (g.ny + 7) / 8;
+    A.nk = (g.nz + 7) / 8;
+    A.ncs = (g.nx + GS_C - 1) / GS_C;
+    A.ncl = (g.nx + 1 + GS_C - 1) / GS_C;
+    A.nb = (g.nx + 14 + GS_C - 1) / GS_C;
+    if (A.nj > 1024 || A.nk > 1024 || S > 4095) {
+        if (err) *err = "Gauss-Seidel grid too large for one launch (ny, nz <= 8192)";
+        return hipErrorInvalidValue;
+    }
+    GsBuffers *B = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_gs_mu);
+        e = get_bufs(dev, s, A.nj * A.nk, &B);
+        if (e != hipSuccess) return e;
+        uint32_t *items = nullptr;
+        e = get_items(dev, A.nj, A.nk, S, &items, &A.nitems);
+        if (e != hipSuccess) return e;
+        A.items = items;
+        A.progress = B->progress;
+        A.ticket = B->ticket;
+    }
+    hipLaunchKernelGGL(gs_reset_kernel, dim3(64), dim3(256), 0, s, A.progress, A.nj * A.nk,
+                       A.ticket);
+    int per_cu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void *>(gs_wavefront_kernel<T, HAS_A, HAS_F>), 64, 0);
+    if (e != hipSuccess || per_cu < 1) per_cu = 1;
+    int ncu = 256;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
+    int grid = per_cu * ncu;
+    if ((uint32_t)grid > A.nitems) grid = (int)A.nitems;
+    hipLaunchKernelGGL((gs_wavefront_kernel<T, HAS_A, HAS_F>), dim3(grid), dim3(64), 0, s, A);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gs_any(const Geom &g, void *u, const void *f, double a, double b, double gw,
+                         int S, hipStream_t s, std::string *err) {
+    const bool ha = a != 0.0, hf = f != nullptr;
+    if (ha && hf) return launch_gs_t<T, true, true>(g, u, f, a, b, gw, S, s, err);
+    if (ha) return launch_gs_t<T, true, false>(g, u, f, a, b, gw, S, s, err);
+    if (hf) return launch_gs_t<T, false, true>(g, u, f, a, b, gw, S, s, err);
+    return launch_gs_t<T, false, false>(g, u, f, a, b, gw, S, s, err);
+}
+
+}  // namespace
+
+hipError_t launch_gs(bool fp32, const Geom &g, void *u, const void *f, double a, double b,
+                     double gw, int sweeps, hipStream_t s, std::string *err) {
+    return fp32 ? launch_gs_any<float>(g, u, f, a, b, gw, sweeps, s, err)
+                : launch_gs_any<double>(g, u, f, a, b, gw, sweeps, s, err);
+}
+
+}  // namespace stk

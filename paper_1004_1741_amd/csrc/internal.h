@@ -1,0 +1,71 @@
+// internal.h -- declarations shared by the HIP kernels and the host runtime of
+// libstencil.  Not part of the public ABI (include/stencil.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+namespace stk {
+
+// Grid geometry in elements (padded layout, x contiguous).
+struct Geom {
+    int nx, ny, nz, h;
+    int64_t px, py, pz;  // padded extents
+    int64_t plane() const { return px * py; }
+    int64_t count() const { return px * py * pz; }
+    int64_t interior() const { return (int64_t)nx * ny * nz; }
+};
+
+// Per-(dtype, TB) tile configuration of the fused Jacobi pass.
+struct JacTileCfg {
+    int tb;     // time levels kept on chip (sweeps per pass)
+    int vx;     // x points per lane (16-byte vectors when vx * sizeof(T) == 16)
+    int ry;     // rows per wave
+    int nw;     // waves per workgroup
+    int tx() const { return 64 * vx; }
+    int ty() const { return nw * ry; }
+    int ow() const { return tx() - 2 * tb - (vx - 1); }  // output tile width
+    int oh() const { return ty() - 2 * tb; }             // output tile height
+};
+
+JacTileCfg jacobi_tile_cfg(bool fp32, int tb);
+
+// One fused Jacobi pass: dst <- TB sweeps of src (interior only).
+// zc = output planes per z-chunk (0 = planner choice).
+hipError_t launch_jacobi_pass(bool fp32, int tb, const Geom &g, const void *src, void *dst,
+                              const void *f, double a, double b, double gw, int zc,
+                              hipStream_t s);
+
+// Ghost-layer helpers (all ghost cells of a padded grid).
+hipError_t launch_fill_ghosts(bool fp32, const Geom &g, void *u, double value, hipStream_t s);
+hipError_t launch_copy_ghosts(bool fp32, const Geom &g, const void *src, void *dst,
+                              hipStream_t s);
+hipError_t launch_copy_interior(bool fp32, const Geom &g, const void *src, void *dst,
+                                hipStream_t s);
+hipError_t launch_zero(void *p, int64_t bytes, hipStream_t s);
+
+// FP64 residual r = f' - ((6c) - s) as double and/or float, with per-block
+// partial sums of r^2 written to partials[nblocks]; returns nblocks.
+hipError_t launch_residual_poisson(const Geom &g, const double *u, const double *fp, double *r64,
+                                   float *r32, double *partials, int *nblocks, hipStream_t s);
+// Generic defect r = (one update of u) - c (FP64), written as float and/or double.
+hipError_t launch_defect(const Geom &g, const double *u, const double *f, double a, double b,
+                         double gw, double *r64, float *r32, hipStream_t s);
+// Deterministic fixed-tree sum of partials[n] into out[0].
+hipError_t launch_sum_partials(const double *partials, int n, double *out, hipStream_t s);
+int residual_partial_count(const Geom &g);
+// u(interior) += (double)e(interior); e padded float or double grid of same geometry.
+hipError_t launch_correct(const Geom &g, double *u, const void *e, bool e_fp32, hipStream_t s);
+
+// Gauss-Seidel wavefront (all sweeps of one launch).
+struct GsPlan;
+hipError_t launch_gs(bool fp32, const Geom &g, void *u, const void *f, double a, double b,
+                     double gw, int sweeps, hipStream_t s, std::string *err);
+
+// Thread-local error message used by the C ABI.
+void set_error(const std::string &msg);
+
+}  // namespace stk

@@ -1,0 +1,450 @@
+// jacobi.hip -- fused multi-sweep Jacobi pass (gfx950).
+//
+// Method (Sec. 3 Jacobi loop nest; Sec. 4 temporal wavefront blocking):
+// TB consecutive Jacobi sweeps are applied in ONE pass over HBM.  The paper
+// gives each of t threads sharing a cache one sweep, shifted in z, with a
+// barrier after every plane.  Here one workgroup owns an x-y tile of the grid
+// and marches it through z; the TB time levels of the tile live on chip:
+//
+//   * a wave covers 64*VX consecutive x sites (16-byte vector loads) and RY
+//     rows; NW waves stack in y, so a tile is (64*VX) x (NW*RY) sites;
+//   * level tau of plane p needs level tau-1 at planes p-1, p, p+1.  With a
+//     skew of one plane per level, step s loads plane s of level 0 and
+//     produces plane s-tau of level tau; the z-1 neighbour stays in a
+//     register ("prev") and the in-plane part of the sum is formed one step
+//     early ("q"), so each level keeps two planes in registers;
+//   * x neighbours come from adjacent lanes through DPP wave shifts, y
+//     neighbours from the thread's own rows or, at wave edges, through a
+//     small double-buffered LDS exchange (one barrier per level per step);
+//   * tiles overlap by TB sites on each side (the dependency cone), so only
+//     the centre (64*VX - 2*TB - VX + 1) x (NW*RY - 2*TB) sites are stored;
+//     ghost cells inside a tile keep their Dirichlet value at every level;
+//   * z is split into chunks; a chunk starts TB planes early to fill the
+//     pipeline (or at the ghost plane, where all levels are known).
+//
+// HBM sees one load of level 0 and one store of level TB per site per pass:
+// 2*sizeof(T) bytes per site per TB sweeps (Eq. (1) with the traffic divided
+// by the number of fused sweeps).  All arithmetic keeps the canonical order
+//   s = ((((x- + x+) + y-) + y+) + z-) + z+,  v = (a*c) + (b*s) [+ g*f]
+// without FMA contraction, so every TB gives results bit-identical to TB
+// sequential sweeps.
+#include "internal.h"
+
+#pragma clang fp contract(off)
+
+namespace stk {
+namespace {
+
+template <typename T, int VX>
+struct VecT;
+template <>
+struct VecT<double, 2> {
+    typedef double type __attribute__((ext_vector_type(2), aligned(8)));
+};
+template <>
+struct VecT<float, 4> {
+    typedef float type __attribute__((ext_vector_type(4), aligned(4)));
+};
+template <>
+struct VecT<float, 2> {
+    typedef float type __attribute__((ext_vector_type(2), aligned(4)));
+};
+
+// Value held by lane l-1 (lane 0 receives 0): DPP wave_shr:1.
+__device__ __forceinline__ float from_lower_lane(float v) {
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+// Value held by lane l+1 (lane 63 receives 0): DPP wave_shl:1.
+__device__ __forceinline__ float from_upper_lane(float v) {
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double from_lower_lane(double v) {
+    int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, false);
+    int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double from_upper_lane(double v) {
+    int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, false);
+    int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+template <typename T>
+struct JacArgs {
+    const T *src;
+    T *dst;
+    const T *f;      // interior-only right-hand side or nullptr
+    int64_t px;      // row pitch (elements)
+    int64_t plane;   // plane pitch (elements)
+    int nx, ny, nz, h;
+    T a, b, g;
+    int tiles_x, tiles_y, nchunks, zc, ow, oh, ntiles;
+};
+
+template <typename T, int VX, bool EDGE>
+__device__ __forceinline__ void load_row(const T *__restrict__ p, unsigned okmask, T (&out)[VX]) {
+    if constexpr (!EDGE && (VX * sizeof(T) == 16 || (VX == 2 && sizeof(T) == 4))) {
+        typedef typename VecT<T, VX>::type V;
+        V v = *reinterpret_cast<const V *>(p);
+#pragma unroll
+        for (int i = 0; i < VX; ++i) out[i] = v[i];
+    } else {
+#pragma unroll
+        for (int i = 0; i < VX; ++i) out[i] = (okmask >> i & 1u) ? p[i] : T(0);
+    }
+}
+
+template <typename T, int VX>
+__device__ __forceinline__ void store_row(T *__restrict__ p, unsigned mask, const T (&v)[VX]) {
+    constexpr unsigned full = (1u << VX) - 1u;
+    if constexpr (VX * sizeof(T) == 16 || (VX == 2 && sizeof(T) == 4)) {
+        if (mask == full) {
+            typedef typename VecT<T, VX>::type V;
+            V w;
+#pragma unroll
+            for (int i = 0; i < VX; ++i) w[i] = v[i];
+            *reinterpret_cast<V *>(p) = w;
+            return;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < VX; ++i)
+        if (mask >> i & 1u) p[i] = v[i];
+}
+
+template <typename T, int TB, int VX, int RY, int NW, bool HAS_A, bool HAS_F, bool EDGE>
+__device__ __forceinline__ void jacobi_tile(const JacArgs<T> &A, int tx, int ty, int cz,
+                                            T (*xch)[NW][2][64 * VX]) {
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int h = A.h;
+
+    // ---- tile geometry (padded coordinates) ----
+    const int ox0 = h + tx * A.ow;
+    const int ox1 = min(ox0 + A.ow, h + A.nx);
+    int xs = ox0 - TB;
+    xs -= ((xs % VX) + VX) % VX;  // align the tile start to the vector width
+    const int oy0 = h + ty * A.oh;
+    const int oy1 = min(oy0 + A.oh, h + A.ny);
+    const int ys = oy0 - TB;
+    const int z0 = h + cz * A.zc;
+    const int z1 = min(z0 + A.zc, h + A.nz);
+    int zb = z0 - TB;
+    if (zb < h - 1) zb = h - 1;          // never below the ghost plane
+    int ze = z1 - 1 + TB;
+    bool top_bnd = false;
+    if (ze >= h + A.nz) { ze = h + A.nz; top_bnd = true; }  // ghost plane on top
+
+    const int x0 = xs + lane * VX;  // this lane's first x
+    const int y0 = ys + w * RY;     // this wave's first row
+
+    // ---- per-thread masks ----
+    unsigned ldx = 0, updx = 0, stx = 0, ldy = 0, updy = 0, sty = 0;
+#pragma unroll
+    for (int v = 0; v < VX; ++v) {
+        const int x = x0 + v;
+        ldx |= (x >= 0 && x < A.nx + 2 * h) ? (1u << v) : 0u;
+        updx |= (x >= h && x < h + A.nx) ? (1u << v) : 0u;
+        stx |= (x >= ox0 && x < ox1) ? (1u << v) : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        const int y = y0 + r;
+        ldy |= (y >= 0 && y < A.ny + 2 * h) ? (1u << r) : 0u;
+        updy |= (y >= h && y < h + A.ny) ? (1u << r) : 0u;
+        sty |= (y >= oy0 && y < oy1) ? (1u << r) : 0u;
+    }
+    // element offset of (row r, x0) within a plane; rows outside the array are
+    // never dereferenced (EDGE masks), so clamping them keeps offsets sane.
+    int rowoff[RY];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        int y = y0 + r;
+        if (EDGE) y = min(max(y, 0), A.ny + 2 * h - 1);
+        rowoff[r] = y * (int)A.px + x0;
+    }
+
+    auto load_plane = [&](int z, T (&out)[RY][VX]) {
+        const T *base = A.src + (int64_t)z * A.plane;
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            const unsigned ok = (ldy >> r & 1u) ? ldx : 0u;
+            load_row<T, VX, EDGE>(base + rowoff[r], ok, out[r]);
+        }
+    };
+    auto load_f = [&](int z, T (&out)[RY][VX]) {
+        // f is interior-only: f[((z-h)*ny + (y-h))*nx + (x-h)]
+        const T *base = A.f + ((int64_t)(z - h) * A.ny) * A.nx;
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            const unsigned ok = (updy >> r & 1u) ? updx : 0u;
+            const int y = EDGE ? min(max(y0 + r, h), h + A.ny - 1) : y0 + r;
+            load_row<T, VX, EDGE>(base + (int64_t)(y - h) * A.nx + (x0 - h), ok, out[r]);
+        }
+    };
+
+    T prev[TB][RY][VX];  // prev[k]: newest plane of level k (the z- of level k+1)
+    T q[TB][RY][VX];     // q[k]: in-plane sum + z- pending for level k+1
+    T cur[RY][VX];
+    T nxt[RY][VX];
+
+    // prologue: the bottom plane zb is known at every level (ghost plane, or
+    // a warm-up plane whose levels are never used for stored outputs)
+    load_plane(zb, cur);
+#pragma unroll
+    for (int k = 0; k < TB; ++k)
+#pragma unroll
+        for (int r = 0; r < RY; ++r)
+#pragma unroll
+            for (int v = 0; v < VX; ++v) prev[k][r][v] = cur[r][v], q[k][r][v] = T(0);
+
+    if (zb + 1 <= ze) load_plane(zb + 1, nxt);
+    int par = 0;  // LDS exchange buffer parity (toggles per exchange)
+    const int s_end = z1 - 1 + TB;
+
+    for (int s = zb + 1; s <= s_end; ++s) {
+        // level 0 of plane s (prefetched), then prefetch plane s+1
+        if (s <= ze) {
+#pragma unroll
+            for (int r = 0; r < RY; ++r)
+#pragma unroll
+                for (int v = 0; v < VX; ++v) cur[r][v] = nxt[r][v];
+            if (s + 1 <= ze) load_plane(s + 1, nxt);
+        }
+#pragma unroll
+        for (int tau = 1; tau <= TB; ++tau) {
+            const int p = s - tau;     // plane produced by level tau
+            const int pin = p + 1;     // plane of `cur` (level tau-1)
+            const int ce_prev = (tau - 1 == 0) ? ze : (top_bnd ? ze - 1 : ze - (tau - 1));
+            const int ce = top_bnd ? ze - 1 : ze - tau;
+            // level tau-1 at the top ghost plane: every level equals the ghost value
+            if (tau >= 2 && top_bnd && pin == ze) load_plane(ze, cur);
+            const bool cur_ok = (pin >= zb + 1) && (pin <= ce_prev || (top_bnd && pin == ze));
+            const bool produce = (p >= zb + 1) && (p <= ce);
+            const bool formq = (pin >= zb + 1) && (pin <= ce);
+
+            T nv[RY][VX];
+            if (produce) {
+                T fv[RY][VX];
+                if constexpr (HAS_F) load_f(p, fv);
+#pragma unroll
+                for (int r = 0; r < RY; ++r)
+#pragma unroll
+                    for (int v = 0; v < VX; ++v) {
+                        const T sum = q[tau - 1][r][v] + cur[r][v];  // + z+
+                        T val;
+                        if constexpr (HAS_A)
+                            val = (A.a * prev[tau - 1][r][v]) + (A.b * sum);
+                        else
+                            val = A.b * sum;
+                        if constexpr (HAS_F) val = val + (A.g * fv[r][v]);
+                        if constexpr (EDGE) {
+                            const bool up = (updy >> r & 1u) && (updx >> v & 1u);
+                            val = up ? val : prev[tau - 1][r][v];
+                        }
+                        nv[r][v] = val;
+                    }
+            }
+            if (formq) {
+                // in-plane neighbours of level tau-1 at plane pin
+                T lft[RY], rgt[RY], ytop[VX], ybot[VX];
+#pragma unroll
+                for (int r = 0; r < RY; ++r) {
+                    lft[r] = from_lower_lane(cur[r][VX - 1]);
+                    rgt[r] = from_upper_lane(cur[r][0]);
+                }
+                if constexpr (NW > 1) {
+                    T *xb0 = &xch[par][w][0][lane * VX];
+                    T *xb1 = &xch[par][w][1][lane * VX];
+#pragma unroll
+                    for (int v = 0; v < VX; ++v) xb0[v] = cur[0][v], xb1[v] = cur[RY - 1][v];
+                    __syncthreads();
+                    const T *up = &xch[par][w > 0 ? w - 1 : w][1][lane * VX];
+                    const T *dn = &xch[par][w < NW - 1 ? w + 1 : w][0][lane * VX];
+#pragma unroll
+                    for (int v = 0; v < VX; ++v) ytop[v] = up[v], ybot[v] = dn[v];
+                    par ^= 1;
+                } else {
+#pragma unroll
+                    for (int v = 0; v < VX; ++v) ytop[v] = cur[0][v], ybot[v] = cur[RY - 1][v];
+                }
+#pragma unroll
+                for (int r = 0; r < RY; ++r)
+#pragma unroll
+                    for (int v = 0; v < VX; ++v) {
+                        const T xm = (v > 0) ? cur[r][v - 1] : lft[r];
+                        const T xp = (v < VX - 1) ? cur[r][v + 1] : rgt[r];
+                        const T ym = (r > 0) ? cur[r - 1][v] : ytop[v];
+                        const T yp = (r < RY - 1) ? cur[r + 1][v] : ybot[v];
+                        q[tau - 1][r][v] = (((xm + xp) + ym) + yp) + prev[tau - 1][r][v];
+                    }
+            }
+            if (cur_ok) {
+#pragma unroll
+                for (int r = 0; r < RY; ++r)
+#pragma unroll
+                    for (int v = 0; v < VX; ++v) prev[tau - 1][r][v] = cur[r][v];
+            }
+            if (produce) {
+#pragma unroll
+                for (int r = 0; r < RY; ++r)
+#pragma unroll
+                    for (int v = 0; v < VX; ++v) cur[r][v] = nv[r][v];
+            }
+        }
+        // store level TB of plane s-TB
+        const int p = s - TB;
+        if (p >= z0 && p < z1) {
+            T *base = A.dst + (int64_t)p * A.plane;
+#pragma unroll
+            for (int r = 0; r < RY; ++r)
+                if (sty >> r & 1u) store_row<T, VX>(base + rowoff[r], stx, cur[r]);
+        }
+    }
+}
+
+template <typename T, int TB, int VX, int RY, int NW, bool HAS_A, bool HAS_F>
+__global__ void __launch_bounds__(NW * 64) jacobi_pass_kernel(JacArgs<T> A) {
+    __shared__ T xch[2][NW][2][64 * VX];
+    // The dispatcher places consecutive workgroup ids round-robin on the 8
+    // XCDs; give each XCD a contiguous range of tiles so that neighbouring
+    // tiles (which re-read each other's overlap) share an L2.
+    const int G = gridDim.x;
+    const int per = G >> 3;
+    const int bid = blockIdx.x;
+    const int l = (bid & 7) * per + (bid >> 3);
+    if (l >= A.ntiles) return;
+    const int tpc = A.tiles_x * A.tiles_y;
+    const int cz = l / tpc;
+    const int rem = l - cz * tpc;
+    const int ty = rem / A.tiles_x;
+    const int tx = rem - ty * A.tiles_x;
+
+    // interior tile: the whole loaded footprint lies inside the interior
+    const int ox0 = A.h + tx * A.ow;
+    int xs = ox0 - TB;
+    xs -= ((xs % VX) + VX) % VX;
+    const int ys = A.h + ty * A.oh - TB;
+    const bool interior = xs >= A.h && xs + 64 * VX <= A.h + A.nx && ys >= A.h &&
+                          ys + NW * RY <= A.h + A.ny;
+    if (interior)
+        jacobi_tile<T, TB, VX, RY, NW, HAS_A, HAS_F, false>(A, tx, ty, cz, xch);
+    else
+        jacobi_tile<T, TB, VX, RY, NW, HAS_A, HAS_F, true>(A, tx, ty, cz, xch);
+}
+
+// Tile configurations.  Register demand per thread is about
+// (2*TB + 3) * RY * VX values; the shapes keep it within 256 VGPRs (two
+// waves per SIMD) while making the tile as large as possible against the
+// 2*TB overlap.
+template <typename T, int TB>
+struct Cfg;
+template <> struct Cfg<double, 1> { static constexpr int VX = 2, RY = 4, NW = 8; };
+template <> struct Cfg<double, 2> { static constexpr int VX = 2, RY = 4, NW = 8; };
+template <> struct Cfg<double, 4> { static constexpr int VX = 2, RY = 4, NW = 8; };
+template <> struct Cfg<double, 8> { static constexpr int VX = 1, RY = 6, NW = 8; };
+template <> struct Cfg<float, 1> { static constexpr int VX = 4, RY = 4, NW = 8; };
+template <> struct Cfg<float, 2> { static constexpr int VX = 4, RY = 4, NW = 8; };
+template <> struct Cfg<float, 4> { static constexpr int VX = 4, RY = 4, NW = 8; };
+template <> struct Cfg<float, 8> { static constexpr int VX = 2, RY = 6, NW = 8; };
+
+template <typename T, int TB>
+JacTileCfg cfg_of() {
+    return JacTileCfg{TB, Cfg<T, TB>::VX, Cfg<T, TB>::RY, Cfg<T, TB>::NW};
+}
+
+// Number of z-chunks: enough workgroups to fill 256 CUs several times over,
+// but chunks no thinner than 4*TB planes (each chunk re-reads TB planes).
+int choose_chunks(const JacTileCfg &c, const Geom &g, int tiles_xy) {
+    const int target = 2048;
+    int nch = (target + tiles_xy - 1) / tiles_xy;
+    const int minzc = 4 * c.tb > 16 ? 4 * c.tb : 16;
+    int maxch = g.nz / minzc;
+    if (maxch < 1) maxch = 1;
+    if (nch > maxch) nch = maxch;
+    if (nch < 1) nch = 1;
+    return nch;
+}
+
+template <typename T, int TB, bool HAS_A, bool HAS_F>
+hipError_t launch_t(const Geom &g, const void *src, void *dst, const void *f, double a, double b,
+                    double gw, int zc, hipStream_t s) {
+    using C = Cfg<T, TB>;
+    const JacTileCfg c = cfg_of<T, TB>();
+    JacArgs<T> A;
+    A.src = static_cast<const T *>(src);
+    A.dst = static_cast<T *>(dst);
+    A.f = static_cast<const T *>(f);
+    A.px = g.px;
+    A.plane = g.plane();
+    A.nx = g.nx; A.ny = g.ny; A.nz = g.nz; A.h = g.h;
+    A.a = (T)a; A.b = (T)b; A.g = (T)gw;
+    A.ow = c.ow();
+    A.oh = c.oh();
+    A.tiles_x = (g.nx + A.ow - 1) / A.ow;
+    A.tiles_y = (g.ny + A.oh - 1) / A.oh;
+    const int tiles_xy = A.tiles_x * A.tiles_y;
+    if (zc <= 0) {
+        const int nch = choose_chunks(c, g, tiles_xy);
+        zc = (g.nz + nch - 1) / nch;
+    }
+    A.zc = zc;
+    A.nchunks = (g.nz + zc - 1) / zc;
+    A.ntiles = tiles_xy * A.nchunks;
+    const int grid = ((A.ntiles + 7) / 8) * 8;
+    hipLaunchKernelGGL((jacobi_pass_kernel<T, TB, C::VX, C::RY, C::NW, HAS_A, HAS_F>),
+                       dim3(grid), dim3(C::NW * 64), 0, s, A);
+    return hipGetLastError();
+}
+
+template <typename T, int TB>
+hipError_t launch_tb(const Geom &g, const void *src, void *dst, const void *f, double a,
+                     double b, double gw, int zc, hipStream_t s) {
+    const bool ha = (a != 0.0), hf = (f != nullptr);
+    if (ha && hf) return launch_t<T, TB, true, true>(g, src, dst, f, a, b, gw, zc, s);
+    if (ha) return launch_t<T, TB, true, false>(g, src, dst, f, a, b, gw, zc, s);
+    if (hf) return launch_t<T, TB, false, true>(g, src, dst, f, a, b, gw, zc, s);
+    return launch_t<T, TB, false, false>(g, src, dst, f, a, b, gw, zc, s);
+}
+
+template <typename T>
+hipError_t launch_any(int tb, const Geom &g, const void *src, void *dst, const void *f, double a,
+                      double b, double gw, int zc, hipStream_t s) {
+    switch (tb) {
+        case 1: return launch_tb<T, 1>(g, src, dst, f, a, b, gw, zc, s);
+        case 2: return launch_tb<T, 2>(g, src, dst, f, a, b, gw, zc, s);
+        case 4: return launch_tb<T, 4>(g, src, dst, f, a, b, gw, zc, s);
+        case 8: return launch_tb<T, 8>(g, src, dst, f, a, b, gw, zc, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+JacTileCfg jacobi_tile_cfg(bool fp32, int tb) {
+    if (fp32) {
+        switch (tb) {
+            case 1: return cfg_of<float, 1>();
+            case 2: return cfg_of<float, 2>();
+            case 4: return cfg_of<float, 4>();
+            default: return cfg_of<float, 8>();
+        }
+    }
+    switch (tb) {
+        case 1: return cfg_of<double, 1>();
+        case 2: return cfg_of<double, 2>();
+        case 4: return cfg_of<double, 4>();
+        default: return cfg_of<double, 8>();
+    }
+}
+
+hipError_t launch_jacobi_pass(bool fp32, int tb, const Geom &g, const void *src, void *dst,
+                              const void *f, double a, double b, double gw, int zc,
+                              hipStream_t s) {
+    return fp32 ? launch_any<float>(tb, g, src, dst, f, a, b, gw, zc, s)
+                : launch_any<double>(tb, g, src, dst, f, a, b, gw, zc, s);
+}
+
+}  // namespace stk
