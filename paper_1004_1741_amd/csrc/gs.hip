@@ -23,9 +23,10 @@
 //     2*tau + J + K, a topological order of their dependencies, so a wave only
 //     ever waits on items already held by running waves (no deadlock, no
 //     co-residency requirement).  Instead of barriers, a wave publishes a
-//     monotone progress counter per bundle after storing each chunk and polls
-//     its neighbours' counters before loading one (acquire/release at agent
-//     scope, across XCDs);
+//     progress counter (chunks stored) per (sweep, bundle) after storing each
+//     chunk and polls its neighbours' counters before loading one
+//     (acquire/release at agent scope, across XCDs).  Counters are per sweep
+//     because several sweeps of one bundle are in flight at once;
 //   * all sweeps of a launch are in flight at once: sweep tau+1 of a bundle
 //     trails sweep tau by a few chunks, so the intermediate sweeps of a band
 //     of the grid are re-read from L2/MALL instead of HBM.
@@ -60,13 +61,9 @@ struct GsArgs {
     int nb;              // step blocks
     uint32_t nitems;
     const uint32_t *items;   // (tau << 20) | (J << 10) | K, topologically ordered
-    uint32_t *progress;      // per bundle, monotone
+    uint32_t *progress;      // [sweep][bundle]: chunks stored so far
     uint32_t *ticket;
 };
-
-__device__ __forceinline__ uint32_t done_mark(int tau, int c, int ncs) {
-    return (uint32_t)tau * (uint32_t)(ncs + 1) + (uint32_t)c + 1u;
-}
 
 __device__ __forceinline__ void wait_at_least(const uint32_t *p, uint32_t need) {
     while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need)
@@ -104,20 +101,21 @@ __global__ void __launch_bounds__(64) gs_wavefront_kernel(GsArgs<T> A) {
         const int j0 = h + 8 * J, k0 = h + 8 * K;
         const int j = j0 + jj, k = k0 + kk;
         const bool active = (j < h + A.ny) && (k < h + A.nz);
-        uint32_t *P = A.progress;
+        const int nbun = A.nj * A.nk;
         const int me = K * A.nj + J;
+        uint32_t *Pcur = A.progress + (size_t)tau * nbun;          // this sweep
+        uint32_t *Pprev = Pcur - nbun;                              // previous sweep
 
         auto wait_chunk = [&](int c) {
             if (c * GS_C >= A.nx) return;  // only the x+ ghost column: never written
+            const uint32_t need = (uint32_t)c + 1u;
             if (tau > 0) {
-                const uint32_t need = done_mark(tau - 1, c, A.ncs);
-                wait_at_least(P + me, need);
-                if (J + 1 < A.nj) wait_at_least(P + me + 1, need);
-                if (K + 1 < A.nk) wait_at_least(P + me + A.nj, need);
+                wait_at_least(Pprev + me, need);                         // own lines, old
+                if (J + 1 < A.nj) wait_at_least(Pprev + me + 1, need);    // y+ halo, old
+                if (K + 1 < A.nk) wait_at_least(Pprev + me + A.nj, need); // z+ halo, old
             }
-            const uint32_t need_new = done_mark(tau, c, A.ncs);
-            if (J > 0) wait_at_least(P + me - 1, need_new);
-            if (K > 0) wait_at_least(P + me - A.nj, need_new);
+            if (J > 0) wait_at_least(Pcur + me - 1, need);                // y- halo, new
+            if (K > 0) wait_at_least(Pcur + me - A.nj, need);             // z- halo, new
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         };
         auto load_chunk = [&](int c) {
@@ -163,7 +161,7 @@ __global__ void __launch_bounds__(64) gs_wavefront_kernel(GsArgs<T> A) {
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             if (lane == 0)
-                __hip_atomic_store(P + me, done_mark(tau, c, A.ncs), __ATOMIC_RELAXED,
+                __hip_atomic_store(Pcur + me, (uint32_t)c + 1u, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
         };
 
@@ -274,19 +272,19 @@ hipError_t get_items(int dev, int nj, int nk, int S, uint32_t **out, uint32_t *c
     return hipSuccess;
 }
 
-hipError_t get_bufs(int dev, hipStream_t s, int nbundles, GsBuffers **out) {
+hipError_t get_bufs(int dev, hipStream_t s, int ncounters, GsBuffers **out) {
     GsBuffers &B = g_gs_bufs[std::make_pair(dev, s)];
-    if (B.cap < nbundles) {
+    if (B.cap < ncounters) {
         if (B.progress) (void)hipFree(B.progress);
         if (B.ticket) (void)hipFree(B.ticket);
         B.progress = nullptr;
         B.ticket = nullptr;
         B.cap = 0;
-        hipError_t e = hipMalloc(&B.progress, (size_t)nbundles * sizeof(uint32_t));
+        hipError_t e = hipMalloc(&B.progress, (size_t)ncounters * sizeof(uint32_t));
         if (e != hipSuccess) return e;
         e = hipMalloc(&B.ticket, 256);
         if (e != hipSuccess) return e;
-        B.cap = nbundles;
+        B.cap = ncounters;
     }
     *out = &B;
     return hipSuccess;
@@ -317,7 +315,7 @@ hipError_t launch_gs_t(const Geom &g, void *u, const void *f, double a, double b
     GsBuffers *B = nullptr;
     {
         std::lock_guard<std::mutex> lk(g_gs_mu);
-        e = get_bufs(dev, s, A.nj * A.nk, &B);
+        e = get_bufs(dev, s, S * A.nj * A.nk, &B);
         if (e != hipSuccess) return e;
         uint32_t *items = nullptr;
         e = get_items(dev, A.nj, A.nk, S, &items, &A.nitems);
@@ -326,8 +324,8 @@ hipError_t launch_gs_t(const Geom &g, void *u, const void *f, double a, double b
         A.progress = B->progress;
         A.ticket = B->ticket;
     }
-    hipLaunchKernelGGL(gs_reset_kernel, dim3(64), dim3(256), 0, s, A.progress, A.nj * A.nk,
-                       A.ticket);
+    hipLaunchKernelGGL(gs_reset_kernel, dim3(256), dim3(256), 0, s, A.progress,
+                       S * A.nj * A.nk, A.ticket);
     int per_cu = 0;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
         &per_cu, reinterpret_cast<const void *>(gs_wavefront_kernel<T, HAS_A, HAS_F>), 64, 0);
