@@ -1,0 +1,222 @@
+#!/usr/bin/env python3
+"""Benchmark of the iterated 3D 7-point smoothers on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--quick] [--no-cpu]
+
+One *step* is the headline workload: 100 FP64 Jacobi sweeps on a 512^3
+interior (ghost and interior values U[0,1), a = 0, b = 1/6), fused t sweeps
+per pass over HBM (t chosen by the library unless --t is given).  The value is
+MLUP/s = 512^3 * 100 * K / (time of K steps); inputs are resident in HBM
+before the timed region.  Extra fields report every t, FP32 storage, the
+Gauss-Seidel wavefront on 384^3 x 50, the FP32-refined vs plain FP64 Poisson
+solve, and the serving stream, each measured after the headline.
+
+The roofline object prices the dominant kernel (the fused Jacobi pass) against
+8 TB/s: algorithmic bytes per pass = 2 * sizeof(double) * 512^3 (one load and
+one store per site, Eq. (1) of the paper divided over t fused sweeps).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--sweeps", type=int, default=100)
+    ap.add_argument("--t", type=int, default=0, help="fused sweeps per pass (0 = library choice)")
+    ap.add_argument("--quick", action="store_true", help="headline only")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--poisson-n", type=int, default=256)
+    ap.add_argument("--serving-jobs", type=int, default=300)
+    ap.add_argument("--serving-rate", type=float, default=200.0)
+    return ap.parse_args()
+
+
+def events_time(torch, fn, reps=1):
+    """Time fn() reps times on the current stream with HIP events (ms)."""
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s)
+    for _ in range(reps):
+        fn()
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def copy_bandwidth(torch, nbytes=2 << 30):
+    """Achievable HBM bandwidth of a plain device copy (GB/s, read + write)."""
+    n = nbytes // 8
+    a = torch.empty(n, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ms = events_time(torch, lambda: b.copy_(a), reps=10) / 10
+    del a, b
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def jacobi_run(P, torch, u, s, sweeps, t):
+    P.jacobi(u, s, sweeps, a=0.0, b=1.0 / 6.0, t_fuse=t)
+
+
+def cpu_baseline(n, target_s=12.0):
+    """The CPU oracle (single thread, as it stands) on a bounded sample."""
+    import oracle
+    import synthetic_inputs as si
+    lib = oracle.load()
+    u = si.jacobi_512(seed=0, n=n)["u"]
+    # calibrate on 1 sweep, then run enough sweeps for ~target_s seconds
+    t0 = time.perf_counter()
+    oracle.jacobi(u, 1, lib=lib)
+    one = time.perf_counter() - t0
+    S = max(1, min(100, int(target_s / max(one, 1e-3))))
+    t0 = time.perf_counter()
+    oracle.jacobi(u, S, lib=lib)
+    dt = time.perf_counter() - t0
+    lups = float(n) ** 3 * S
+    return {"value": lups / dt / 1e6, "unit": "MLUP/s", "cores": 1, "kind": "oracle",
+            "sample": "FP64 Jacobi %d^3 x %d sweeps (of the 100-sweep step), single-threaded "
+                      "C oracle, %.1f s" % (n, S, dt)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (--gpus %d "
+              "requested); run with --gpus 1" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(2)
+    import paper_1004_1741_amd as P
+    import synthetic_inputs as si
+
+    P.lib()
+    n, S = args.n, args.sweeps
+    lups_step = float(n) ** 3 * S
+    w = si.jacobi_512(seed=0, n=n)
+    u = torch.from_numpy(w["u"]).to("cuda")
+    s = torch.empty_like(u)
+    del w
+    log("device:", torch.cuda.get_device_name(0))
+
+    plan, fcopy = P.jacobi_plan(S, args.t)
+    passes = len(plan)
+
+    for _ in range(args.warmup):
+        jacobi_run(P, torch, u, s, S, args.t)
+    torch.cuda.synchronize()
+    ms = events_time(torch, lambda: jacobi_run(P, torch, u, s, S, args.t), reps=args.steps)
+    ms_step = ms / args.steps
+    value = lups_step / (ms_step * 1e-3) / 1e6
+    log("headline: %.3f ms/step, %.0f MLUP/s, plan %s" % (ms_step, value, plan))
+
+    # dominant kernel: the fused pass; its average launch duration from the same events
+    pass_ms = ms_step / passes
+    pass_bytes = 2 * 8 * float(n) ** 3
+    achieved = pass_bytes / (pass_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "jacobi_pass_kernel<double,t=%d>" % max(plan),
+            "pass_us": round(pass_ms * 1e3, 2), "bytes_per_pass": pass_bytes,
+            "bytes_per_lup": round(16.0 / (S / passes), 3)}
+
+    extra = {}
+    if not args.quick:
+        extra["copy_GBs"] = round(copy_bandwidth(torch), 1)
+        per_t = {}
+        for t in (1, 2, 4, 8, 16):
+            pl, _ = P.jacobi_plan(S, t)
+            jacobi_run(P, torch, u, s, S, t)
+            m = events_time(torch, lambda: jacobi_run(P, torch, u, s, S, t), reps=2) / 2
+            pms = m / len(pl)
+            per_t[str(t)] = {"ms": round(m, 3), "MLUPs": round(lups_step / (m * 1e-3) / 1e6),
+                             "passes": len(pl), "pass_us": round(pms * 1e3, 1),
+                             "pass_GBs": round(pass_bytes / (pms * 1e-3) / 1e9, 1),
+                             "pass_frac": round(pass_bytes / (pms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            log("jacobi fp64 t=%d: %s" % (t, per_t[str(t)]))
+        extra["jacobi_fp64_by_t"] = per_t
+        extra["speedup_best_vs_t1"] = round(
+            max(v["MLUPs"] for v in per_t.values()) / per_t["1"]["MLUPs"], 2)
+        # FP32 storage
+        u32 = u.float()
+        s32 = torch.empty_like(u32)
+        per32 = {}
+        for t in (1, 4, 8):
+            jacobi_run(P, torch, u32, s32, S, t)
+            m = events_time(torch, lambda: jacobi_run(P, torch, u32, s32, S, t), reps=2) / 2
+            pl, _ = P.jacobi_plan(S, t, fp32=True)
+            per32[str(t)] = {"ms": round(m, 3), "MLUPs": round(lups_step / (m * 1e-3) / 1e6),
+                             "passes": len(pl)}
+            log("jacobi fp32 t=%d: %s" % (t, per32[str(t)]))
+        extra["jacobi_fp32_by_t"] = per32
+        del u32, s32
+        # Gauss-Seidel wavefront, 384^3 x 50
+        g = si.gs_384(seed=0)
+        ug = torch.from_numpy(g["u"]).to("cuda")
+        gl = 384.0 ** 3 * g["sweeps"]
+        gs = {}
+        for t in (0, 1):
+            u0 = ug.clone()
+            P.gauss_seidel(u0, g["sweeps"], t_fuse=t)
+            u0.copy_(ug)
+            m = events_time(torch, lambda: P.gauss_seidel(u0, g["sweeps"], t_fuse=t), reps=1)
+            key = "all_sweeps_in_flight" if t == 0 else "one_launch_per_sweep"
+            gs[key] = {"ms": round(m, 3), "MLUPs": round(gl / (m * 1e-3) / 1e6)}
+            log("gs 384^3 x50 %s: %s" % (key, gs[key]))
+        extra["gs_384_x50"] = gs
+        del ug, u0
+        torch.cuda.synchronize()
+
+    line = {
+        "metric": "MLUP/s & HBM-roofline fraction at 512^3 (FP64 vs FP32-refined); job p50/p99",
+        "value": round(value, 1),
+        "unit": "MLUP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "jacobi3d7pt_fp64_%d^3_x%d_sweeps" % (n, S), "interior": n,
+                   "sweeps": S, "t_fuse": args.t, "plan": plan, "final_copy": fcopy,
+                   "parallelism": "single-gpu"},
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(n)
+        line["cpu_baseline"]["host"] = platform.processor() or platform.machine()
+        line["cpu_baseline"]["host_threads_available"] = os.cpu_count()
+    line.update(extra)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

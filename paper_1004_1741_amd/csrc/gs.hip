@@ -65,6 +65,29 @@ struct GsArgs {
     uint32_t *ticket;
 };
 
+// Bundle data crosses workgroups that may sit on different XCDs, whose L2
+// caches are not coherent with each other.  Every access to the grid inside
+// this kernel is a device-scope (agent) relaxed atomic: such loads and stores
+// are coherent across XCDs by themselves, so publishing a chunk only needs the
+// stores to have completed before the progress counter is written, instead of
+// the whole-L2 write-back / invalidate that agent-scope fences would issue for
+// every chunk.
+template <typename T>
+__device__ __forceinline__ T coherent_load(const T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void coherent_store(T *p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Wait until every vector memory operation of this wave has completed
+// (s_waitcnt vmcnt(0); expcnt and lgkmcnt left unconstrained).
+__device__ __forceinline__ void wait_vm_done() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+}
+
 __device__ __forceinline__ void wait_at_least(const uint32_t *p, uint32_t need) {
     while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need)
         __builtin_amdgcn_s_sleep(2);
@@ -106,6 +129,36 @@ __global__ void __launch_bounds__(64) gs_wavefront_kernel(GsArgs<T> A) {
         uint32_t *Pcur = A.progress + (size_t)tau * nbun;          // this sweep
         uint32_t *Pprev = Pcur - nbun;                              // previous sweep
 
+        // Per-item staging tables: lane-constant line pointers and LDS offsets
+        // of the 12 (load) and 8 (store) elements this lane moves per chunk.
+        const T *lsrc[12];
+        int lring[12];
+        bool lok[12];
+#pragma unroll
+        for (int m = 0; m < 12; ++m) {
+            const int e = lane + 64 * m;
+            const int slot = staged_slot(e >> 3);
+            const int jl = slot % 10, kl = slot / 10;
+            const int jg = j0 - 1 + jl, kg = k0 - 1 + kl;
+            lok[m] = jg <= h + A.ny && kg <= h + A.nz;
+            lsrc[m] = A.u + (int64_t)kg * A.plane + (int64_t)jg * A.px + h + (e & 7);
+            lring[m] = slot * GS_S;
+        }
+        T *sdst[8];
+        int sring[8];
+        bool sok[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const int e = lane + 64 * m;
+            const int li = e >> 3;
+            const int jq = li & 7, kq = li >> 3;
+            const int jg = j0 + jq, kg = k0 + kq;
+            sok[m] = jg < h + A.ny && kg < h + A.nz;
+            sdst[m] = A.u + (int64_t)kg * A.plane + (int64_t)jg * A.px + h + (e & 7);
+            sring[m] = ((kq + 1) * 10 + (jq + 1)) * GS_S;
+        }
+        const int xoff = lane & 7;  // position within a chunk of every element
+
         auto wait_chunk = [&](int c) {
             if (c * GS_C >= A.nx) return;  // only the x+ ghost column: never written
             const uint32_t need = (uint32_t)c + 1u;
@@ -116,50 +169,50 @@ __global__ void __launch_bounds__(64) gs_wavefront_kernel(GsArgs<T> A) {
             }
             if (J > 0) wait_at_least(Pcur + me - 1, need);                // y- halo, new
             if (K > 0) wait_at_least(Pcur + me - A.nj, need);             // z- halo, new
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            // keep the coherent data loads below after the counter polls
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         };
         auto load_chunk = [&](int c) {
+            const int i = c * GS_C + xoff;
+            const bool iok = i <= A.nx;
+            const int r = i & (GS_RING - 1);
+            T v[12];
 #pragma unroll
-            for (int m = 0; m < 12; ++m) {
-                const int e = lane + 64 * m;
-                const int li = e >> 3;
-                const int i = c * GS_C + (e & 7);
-                const int slot = staged_slot(li);
-                const int jl = slot % 10, kl = slot / 10;
-                const int jg = j0 - 1 + jl, kg = k0 - 1 + kl;
-                const bool ok = i <= A.nx && jg <= h + A.ny && kg <= h + A.nz;
-                T v = T(0);
-                if (ok) v = A.u[(int64_t)kg * A.plane + (int64_t)jg * A.px + h + i];
-                ring[slot * GS_S + (i & (GS_RING - 1))] = v;
-            }
+            for (int m = 0; m < 12; ++m)
+                v[m] = (iok && lok[m]) ? coherent_load(lsrc[m] + c * GS_C) : T(0);
+#pragma unroll
+            for (int m = 0; m < 12; ++m) ring[lring[m] + r] = v[m];
             if constexpr (HAS_F) {
+                T fv[8];
 #pragma unroll
                 for (int m = 0; m < 8; ++m) {
                     const int e = lane + 64 * m;
-                    const int li = e >> 3;  // own line li = jj' + 8*kk'
-                    const int i = c * GS_C + (e & 7);
+                    const int li = e >> 3;
                     const int jq = li & 7, kq = li >> 3;
                     const int jg = j0 + jq, kg = k0 + kq;
-                    T v = T(0);
-                    if (i < A.nx && jg < h + A.ny && kg < h + A.nz)
-                        v = A.f[((int64_t)(kg - h) * A.ny + (jg - h)) * A.nx + i];
-                    fring[(kq * 10 + jq) * GS_S + (i & (GS_RING - 1))] = v;
+                    fv[m] = (i < A.nx && sok[m])
+                                ? A.f[((int64_t)(kg - h) * A.ny + (jg - h)) * A.nx + i]
+                                : T(0);
+                }
+#pragma unroll
+                for (int m = 0; m < 8; ++m) {
+                    const int li = (lane + 64 * m) >> 3;
+                    fring[((li >> 3) * 10 + (li & 7)) * GS_S + r] = fv[m];
                 }
             }
         };
         auto store_chunk = [&](int c) {
+            const int i = c * GS_C + xoff;
+            const int r = i & (GS_RING - 1);
+            T v[8];
 #pragma unroll
-            for (int m = 0; m < 8; ++m) {
-                const int e = lane + 64 * m;
-                const int li = e >> 3;
-                const int i = c * GS_C + (e & 7);
-                const int jq = li & 7, kq = li >> 3;
-                const int jg = j0 + jq, kg = k0 + kq;
-                if (i < A.nx && jg < h + A.ny && kg < h + A.nz)
-                    A.u[(int64_t)kg * A.plane + (int64_t)jg * A.px + h + i] =
-                        ring[((kq + 1) * 10 + (jq + 1)) * GS_S + (i & (GS_RING - 1))];
+            for (int m = 0; m < 8; ++m) v[m] = ring[sring[m] + r];
+            if (i < A.nx) {
+#pragma unroll
+                for (int m = 0; m < 8; ++m)
+                    if (sok[m]) coherent_store(sdst[m] + c * GS_C, v[m]);
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            wait_vm_done();  // the chunk's stores are complete before it is published
             if (lane == 0)
                 __hip_atomic_store(Pcur + me, (uint32_t)c + 1u, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
