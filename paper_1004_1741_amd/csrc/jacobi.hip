@@ -28,6 +28,8 @@
 //   s = ((((x- + x+) + y-) + y+) + z-) + z+,  v = (a*c) + (b*s) [+ g*f]
 // without FMA contraction, so every TB gives results bit-identical to TB
 // sequential sweeps.
+#include <type_traits>
+
 #include "internal.h"
 
 #pragma clang fp contract(off)
@@ -116,7 +118,7 @@ __device__ __forceinline__ void store_row(T *__restrict__ p, unsigned mask, cons
 
 template <typename T, int TB, int VX, int RY, int NW, bool HAS_A, bool HAS_F, bool EDGE>
 __device__ __forceinline__ void jacobi_tile(const JacArgs<T> &A, int tx, int ty, int cz,
-                                            T (*xch)[NW][2][64 * VX]) {
+                                            T (*xch)[TB][NW][2][64 * VX]) {
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const int h = A.h;
@@ -185,114 +187,120 @@ __device__ __forceinline__ void jacobi_tile(const JacArgs<T> &A, int tx, int ty,
         }
     };
 
-    T prev[TB][RY][VX];  // prev[k]: newest plane of level k (the z- of level k+1)
-    T q[TB][RY][VX];     // q[k]: in-plane sum + z- pending for level k+1
-    T cur[RY][VX];
+    // Two planes per level live in registers, in arrays P0 and P1 whose roles
+    // alternate from step to step.  At the start of step s, "A" holds
+    // A[k] = L_k[s-k-1] (newest plane of level k) and "B" holds
+    // B[k] = L_k[s-k-2]; the edge rows of every A[k] were exchanged through
+    // LDS at the end of the previous step.  Level tau at plane p = s-tau needs
+    // A[tau-1] (centre and in-plane neighbours), B[tau-1][site] (z-) and the
+    // new plane of level tau-1 at the same site (z+); once read, B[tau-1][site]
+    // is dead and is overwritten by that new plane, so after the step the "B"
+    // array holds the newest planes and the roles swap -- no register moves.
+    T P0[TB][RY][VX];
+    T P1[TB][RY][VX];
     T nxt[RY][VX];
 
-    // prologue: the bottom plane zb is known at every level (ghost plane, or
-    // a warm-up plane whose levels are never used for stored outputs)
-    load_plane(zb, cur);
+    auto exchange = [&](int buf, T (&Anew)[TB][RY][VX]) {
+        if constexpr (NW > 1) {
+#pragma unroll
+            for (int k = 0; k < TB; ++k) {
+                T *x0 = &xch[buf][k][w][0][lane * VX];
+                T *x1 = &xch[buf][k][w][1][lane * VX];
+#pragma unroll
+                for (int v = 0; v < VX; ++v) x0[v] = Anew[k][0][v], x1[v] = Anew[k][RY - 1][v];
+            }
+        }
+        __syncthreads();
+    };
+
+    // prologue: plane zb is known at every level (ghost plane, or a warm-up
+    // plane whose levels never reach a stored output)
+    load_plane(zb, nxt);
 #pragma unroll
     for (int k = 0; k < TB; ++k)
 #pragma unroll
         for (int r = 0; r < RY; ++r)
 #pragma unroll
-            for (int v = 0; v < VX; ++v) prev[k][r][v] = cur[r][v], q[k][r][v] = T(0);
-
+            for (int v = 0; v < VX; ++v) P0[k][r][v] = nxt[r][v], P1[k][r][v] = nxt[r][v];
     if (zb + 1 <= ze) load_plane(zb + 1, nxt);
-    int par = 0;  // LDS exchange buffer parity (toggles per exchange)
+    int buf = 0;
+    exchange(buf, P0);
     const int s_end = z1 - 1 + TB;
 
-    for (int s = zb + 1; s <= s_end; ++s) {
-        // level 0 of plane s (prefetched), then prefetch plane s+1
-        if (s <= ze) {
+    // FULL: steady state, every level produces and the next plane exists
+    auto step = [&](int s, T (&Aa)[TB][RY][VX], T (&Bb)[TB][RY][VX], auto full_c) {
+        constexpr bool FULL = decltype(full_c)::value;
+        T Nprev[RY][VX];  // new plane of level tau-1 (level 0: plane s, loaded)
 #pragma unroll
-            for (int r = 0; r < RY; ++r)
+        for (int r = 0; r < RY; ++r)
 #pragma unroll
-                for (int v = 0; v < VX; ++v) cur[r][v] = nxt[r][v];
-            if (s + 1 <= ze) load_plane(s + 1, nxt);
-        }
+            for (int v = 0; v < VX; ++v) Nprev[r][v] = nxt[r][v];
+        if (FULL || s + 1 <= ze) load_plane(s + 1, nxt);
+
 #pragma unroll
         for (int tau = 1; tau <= TB; ++tau) {
-            const int p = s - tau;     // plane produced by level tau
-            const int pin = p + 1;     // plane of `cur` (level tau-1)
-            const int ce_prev = (tau - 1 == 0) ? ze : (top_bnd ? ze - 1 : ze - (tau - 1));
+            const int p = s - tau;  // plane of level tau produced now
             const int ce = top_bnd ? ze - 1 : ze - tau;
-            // level tau-1 at the top ghost plane: every level equals the ghost value
-            if (tau >= 2 && top_bnd && pin == ze) load_plane(ze, cur);
-            const bool cur_ok = (pin >= zb + 1) && (pin <= ce_prev || (top_bnd && pin == ze));
-            const bool produce = (p >= zb + 1) && (p <= ce);
-            const bool formq = (pin >= zb + 1) && (pin <= ce);
-
-            T nv[RY][VX];
-            if (produce) {
+            T Ncur[RY][VX];
+            if (FULL || (p >= zb + 1 && p <= ce)) {
+                // in-plane neighbours of L_{tau-1}[p] = Aa[tau-1]
+                T lft[RY], rgt[RY], ytop[VX], ybot[VX];
+#pragma unroll
+                for (int r = 0; r < RY; ++r) {
+                    lft[r] = from_lower_lane(Aa[tau - 1][r][VX - 1]);
+                    rgt[r] = from_upper_lane(Aa[tau - 1][r][0]);
+                }
+                if constexpr (NW > 1) {
+                    const T *up = &xch[buf][tau - 1][w > 0 ? w - 1 : w][1][lane * VX];
+                    const T *dn = &xch[buf][tau - 1][w < NW - 1 ? w + 1 : w][0][lane * VX];
+#pragma unroll
+                    for (int v = 0; v < VX; ++v) ytop[v] = up[v], ybot[v] = dn[v];
+                } else {
+#pragma unroll
+                    for (int v = 0; v < VX; ++v)
+                        ytop[v] = Aa[tau - 1][0][v], ybot[v] = Aa[tau - 1][RY - 1][v];
+                }
                 T fv[RY][VX];
                 if constexpr (HAS_F) load_f(p, fv);
 #pragma unroll
                 for (int r = 0; r < RY; ++r)
 #pragma unroll
                     for (int v = 0; v < VX; ++v) {
-                        const T sum = q[tau - 1][r][v] + cur[r][v];  // + z+
+                        const T c = Aa[tau - 1][r][v];
+                        const T xm = (v > 0) ? Aa[tau - 1][r][v - 1] : lft[r];
+                        const T xp = (v < VX - 1) ? Aa[tau - 1][r][v + 1] : rgt[r];
+                        const T ym = (r > 0) ? Aa[tau - 1][r - 1][v] : ytop[v];
+                        const T yp = (r < RY - 1) ? Aa[tau - 1][r + 1][v] : ybot[v];
+                        const T sum =
+                            ((((xm + xp) + ym) + yp) + Bb[tau - 1][r][v]) + Nprev[r][v];
                         T val;
                         if constexpr (HAS_A)
-                            val = (A.a * prev[tau - 1][r][v]) + (A.b * sum);
+                            val = (A.a * c) + (A.b * sum);
                         else
                             val = A.b * sum;
                         if constexpr (HAS_F) val = val + (A.g * fv[r][v]);
                         if constexpr (EDGE) {
                             const bool up = (updy >> r & 1u) && (updx >> v & 1u);
-                            val = up ? val : prev[tau - 1][r][v];
+                            val = up ? val : c;
                         }
-                        nv[r][v] = val;
+                        Ncur[r][v] = val;
+                        Bb[tau - 1][r][v] = Nprev[r][v];
                     }
-            }
-            if (formq) {
-                // in-plane neighbours of level tau-1 at plane pin
-                T lft[RY], rgt[RY], ytop[VX], ybot[VX];
-#pragma unroll
-                for (int r = 0; r < RY; ++r) {
-                    lft[r] = from_lower_lane(cur[r][VX - 1]);
-                    rgt[r] = from_upper_lane(cur[r][0]);
-                }
-                if constexpr (NW > 1) {
-                    T *xb0 = &xch[par][w][0][lane * VX];
-                    T *xb1 = &xch[par][w][1][lane * VX];
-#pragma unroll
-                    for (int v = 0; v < VX; ++v) xb0[v] = cur[0][v], xb1[v] = cur[RY - 1][v];
-                    __syncthreads();
-                    const T *up = &xch[par][w > 0 ? w - 1 : w][1][lane * VX];
-                    const T *dn = &xch[par][w < NW - 1 ? w + 1 : w][0][lane * VX];
-#pragma unroll
-                    for (int v = 0; v < VX; ++v) ytop[v] = up[v], ybot[v] = dn[v];
-                    par ^= 1;
-                } else {
-#pragma unroll
-                    for (int v = 0; v < VX; ++v) ytop[v] = cur[0][v], ybot[v] = cur[RY - 1][v];
-                }
+            } else {
+                // no computation at this plane: every level equals the level
+                // below there (ghost planes), or the value is never used
 #pragma unroll
                 for (int r = 0; r < RY; ++r)
 #pragma unroll
                     for (int v = 0; v < VX; ++v) {
-                        const T xm = (v > 0) ? cur[r][v - 1] : lft[r];
-                        const T xp = (v < VX - 1) ? cur[r][v + 1] : rgt[r];
-                        const T ym = (r > 0) ? cur[r - 1][v] : ytop[v];
-                        const T yp = (r < RY - 1) ? cur[r + 1][v] : ybot[v];
-                        q[tau - 1][r][v] = (((xm + xp) + ym) + yp) + prev[tau - 1][r][v];
+                        Ncur[r][v] = Aa[tau - 1][r][v];
+                        Bb[tau - 1][r][v] = Nprev[r][v];
                     }
             }
-            if (cur_ok) {
 #pragma unroll
-                for (int r = 0; r < RY; ++r)
+            for (int r = 0; r < RY; ++r)
 #pragma unroll
-                    for (int v = 0; v < VX; ++v) prev[tau - 1][r][v] = cur[r][v];
-            }
-            if (produce) {
-#pragma unroll
-                for (int r = 0; r < RY; ++r)
-#pragma unroll
-                    for (int v = 0; v < VX; ++v) cur[r][v] = nv[r][v];
-            }
+                for (int v = 0; v < VX; ++v) Nprev[r][v] = Ncur[r][v];
         }
         // store level TB of plane s-TB
         const int p = s - TB;
@@ -300,14 +308,24 @@ __device__ __forceinline__ void jacobi_tile(const JacArgs<T> &A, int tx, int ty,
             T *base = A.dst + (int64_t)p * A.plane;
 #pragma unroll
             for (int r = 0; r < RY; ++r)
-                if (sty >> r & 1u) store_row<T, VX>(base + rowoff[r], stx, cur[r]);
+                if (sty >> r & 1u) store_row<T, VX>(base + rowoff[r], stx, Nprev[r]);
         }
+        buf ^= 1;
+        exchange(buf, Bb);
+    };
+
+    using Part = std::integral_constant<bool, false>;
+    int s = zb + 1;
+    for (; s + 1 <= s_end; s += 2) {
+        step(s, P0, P1, Part{});
+        step(s + 1, P1, P0, Part{});
     }
+    if (s <= s_end) step(s, P0, P1, Part{});
 }
 
 template <typename T, int TB, int VX, int RY, int NW, bool HAS_A, bool HAS_F>
 __global__ void __launch_bounds__(NW * 64) jacobi_pass_kernel(JacArgs<T> A) {
-    __shared__ T xch[2][NW][2][64 * VX];
+    __shared__ T xch[2][TB][NW][2][64 * VX];
     // The dispatcher places consecutive workgroup ids round-robin on the 8
     // XCDs; give each XCD a contiguous range of tiles so that neighbouring
     // tiles (which re-read each other's overlap) share an L2.
