@@ -137,6 +137,12 @@ struct DevBuf {
 
 }  // namespace
 
+namespace stk {
+std::vector<int> jacobi_pass_plan(bool fp32, int sweeps, int t_fuse, bool *final_copy) {
+    return jacobi_plan(fp32 ? ST_FP32 : ST_FP64, sweeps, t_fuse, final_copy);
+}
+}  // namespace stk
+
 extern "C" {
 
 const char *stencil_version(void) { return "libstencil 0.1 (gfx950)"; }

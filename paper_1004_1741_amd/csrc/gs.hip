@@ -49,7 +49,7 @@ constexpr int GS_S = 41;      // LDS stride per line: S = 9 (mod 16) makes the
 constexpr int GS_SLOTS = 100; // 10 x 10 staged lines (corners unused)
 
 template <typename T>
-struct GsArgs {
+struct GsJob {
     T *u;
     const T *f;
     int64_t px, plane;
@@ -59,9 +59,24 @@ struct GsArgs {
     int ncs;             // store chunks per line
     int ncl;             // load chunks per line (includes the x+ ghost)
     int nb;              // step blocks
+    uint32_t *progress;  // [sweep][bundle]: chunks stored so far
+};
+
+template <typename T>
+struct GsArgs {
+    GsJob<T> job;
     uint32_t nitems;
     const uint32_t *items;   // (tau << 20) | (J << 10) | K, topologically ordered
-    uint32_t *progress;      // [sweep][bundle]: chunks stored so far
+    uint32_t *ticket;
+};
+
+// Batched launch: items of several jobs merged in key order; each item is
+// (job << 48) | (tau << 32) | (J << 16) | K.
+template <typename T>
+struct GsBatchArgs {
+    const GsJob<T> *jobs;
+    uint32_t nitems;
+    const uint64_t *items;
     uint32_t *ticket;
 };
 
@@ -100,27 +115,16 @@ __device__ __forceinline__ int staged_slot(int li) {
     return 90 + (li - 88) + 1;                       // kl = 9, jl = 1..8
 }
 
+// One work item: sweep tau of bundle (J, K) of one grid, marched along x.
 template <typename T, bool HAS_A, bool HAS_F>
-__global__ void __launch_bounds__(64) gs_wavefront_kernel(GsArgs<T> A) {
-    __shared__ T ring[GS_SLOTS * GS_S];
-    __shared__ T fring[HAS_F ? 78 * GS_S : 1];
+__device__ __forceinline__ void gs_item(const GsJob<T> &A, int tau, int J, int K, T *ring,
+                                        T *fring) {
     const int lane = threadIdx.x;
     const int kk = lane & 7, jj = lane >> 3;  // kk fastest: conflict-free LDS
     const int d = jj + kk;                    // skew of this lane's line
     const int own = (kk + 1) * 10 + (jj + 1);
     const int fown = kk * 10 + jj;
     const int h = A.h;
-
-    for (;;) {
-        uint32_t t = 0;
-        if (lane == 0)
-            t = __hip_atomic_fetch_add(A.ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        t = __shfl(t, 0, 64);
-        if (t >= A.nitems) break;
-        const uint32_t it = A.items[t];
-        const int tau = (int)(it >> 20);
-        const int J = (int)((it >> 10) & 1023u);
-        const int K = (int)(it & 1023u);
         const int j0 = h + 8 * J, k0 = h + 8 * K;
         const int j = j0 + jj, k = k0 + kk;
         const bool active = (j < h + A.ny) && (k < h + A.nz);
@@ -266,6 +270,38 @@ __global__ void __launch_bounds__(64) gs_wavefront_kernel(GsArgs<T> A) {
             }
         }
         for (int cs = max(0, A.nb - 2); cs < A.ncs; ++cs) store_chunk(cs);
+}
+
+template <typename T, bool HAS_A, bool HAS_F>
+__global__ void __launch_bounds__(64) gs_wavefront_kernel(GsArgs<T> G) {
+    __shared__ T ring[GS_SLOTS * GS_S];
+    __shared__ T fring[HAS_F ? 78 * GS_S : 1];
+    for (;;) {
+        uint32_t t = 0;
+        if (threadIdx.x == 0)
+            t = __hip_atomic_fetch_add(G.ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        t = __shfl(t, 0, 64);
+        if (t >= G.nitems) break;
+        const uint32_t it = G.items[t];
+        gs_item<T, HAS_A, HAS_F>(G.job, (int)(it >> 20), (int)((it >> 10) & 1023u),
+                                 (int)(it & 1023u), ring, fring);
+    }
+}
+
+template <typename T, bool HAS_A, bool HAS_F>
+__global__ void __launch_bounds__(64) gs_batch_kernel(GsBatchArgs<T> G) {
+    __shared__ T ring[GS_SLOTS * GS_S];
+    __shared__ T fring[HAS_F ? 78 * GS_S : 1];
+    for (;;) {
+        uint32_t t = 0;
+        if (threadIdx.x == 0)
+            t = __hip_atomic_fetch_add(G.ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        t = __shfl(t, 0, 64);
+        if (t >= G.nitems) break;
+        const uint64_t it = G.items[t];
+        const GsJob<T> job = G.jobs[(int)(it >> 48)];
+        gs_item<T, HAS_A, HAS_F>(job, (int)((it >> 32) & 0xffffu), (int)((it >> 16) & 0xffffu),
+                                 (int)(it & 0xffffu), ring, fring);
     }
 }
 
@@ -343,13 +379,10 @@ hipError_t get_bufs(int dev, hipStream_t s, int ncounters, GsBuffers **out) {
     return hipSuccess;
 }
 
-template <typename T, bool HAS_A, bool HAS_F>
-hipError_t launch_gs_t(const Geom &g, void *u, const void *f, double a, double b, double gw,
-                       int S, hipStream_t s, std::string *err) {
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return e;
-    GsArgs<T> A;
+template <typename T>
+GsJob<T> make_job(const Geom &g, void *u, const void *f, double a, double b, double gw,
+                  uint32_t *progress) {
+    GsJob<T> A;
     A.u = static_cast<T *>(u);
     A.f = static_cast<const T *>(f);
     A.px = g.px;
@@ -361,34 +394,64 @@ hipError_t launch_gs_t(const Geom &g, void *u, const void *f, double a, double b
     A.ncs = (g.nx + GS_C - 1) / GS_C;
     A.ncl = (g.nx + 1 + GS_C - 1) / GS_C;
     A.nb = (g.nx + 14 + GS_C - 1) / GS_C;
-    if (A.nj > 1024 || A.nk > 1024 || S > 4095) {
+    A.progress = progress;
+    return A;
+}
+
+int device_cus(int dev) {
+    static int cached[64] = {0};
+    if (dev < 0 || dev >= 64) return 256;
+    if (cached[dev] == 0) {
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) !=
+                hipSuccess || ncu < 1)
+            ncu = 256;
+        cached[dev] = ncu;
+    }
+    return cached[dev];
+}
+
+template <typename K>
+int per_cu_occupancy(K kfn) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kfn),
+                                                     64, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    return per_cu;
+}
+
+template <typename T, bool HAS_A, bool HAS_F>
+hipError_t launch_gs_t(const Geom &g, void *u, const void *f, double a, double b, double gw,
+                       int S, hipStream_t s, std::string *err) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    GsArgs<T> G;
+    G.job = make_job<T>(g, u, f, a, b, gw, nullptr);
+    const int nj = G.job.nj, nk = G.job.nk;
+    if (nj > 1024 || nk > 1024 || S > 4095) {
         if (err) *err = "Gauss-Seidel grid too large for one launch (ny, nz <= 8192)";
         return hipErrorInvalidValue;
     }
-    GsBuffers *B = nullptr;
     {
         std::lock_guard<std::mutex> lk(g_gs_mu);
-        e = get_bufs(dev, s, S * A.nj * A.nk, &B);
+        GsBuffers *B = nullptr;
+        e = get_bufs(dev, s, S * nj * nk, &B);
         if (e != hipSuccess) return e;
         uint32_t *items = nullptr;
-        e = get_items(dev, A.nj, A.nk, S, &items, &A.nitems);
+        e = get_items(dev, nj, nk, S, &items, &G.nitems);
         if (e != hipSuccess) return e;
-        A.items = items;
-        A.progress = B->progress;
-        A.ticket = B->ticket;
+        G.items = items;
+        G.job.progress = B->progress;
+        G.ticket = B->ticket;
     }
-    hipLaunchKernelGGL(gs_reset_kernel, dim3(256), dim3(256), 0, s, A.progress,
-                       S * A.nj * A.nk, A.ticket);
-    int per_cu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, reinterpret_cast<const void *>(gs_wavefront_kernel<T, HAS_A, HAS_F>), 64, 0);
-    if (e != hipSuccess || per_cu < 1) per_cu = 1;
-    int ncu = 256;
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
-    int grid = per_cu * ncu;
-    if ((uint32_t)grid > A.nitems) grid = (int)A.nitems;
-    hipLaunchKernelGGL((gs_wavefront_kernel<T, HAS_A, HAS_F>), dim3(grid), dim3(64), 0, s, A);
+    hipLaunchKernelGGL(gs_reset_kernel, dim3(256), dim3(256), 0, s, G.job.progress, S * nj * nk,
+                       G.ticket);
+    static int per_cu = 0;
+    if (per_cu == 0) per_cu = per_cu_occupancy(gs_wavefront_kernel<T, HAS_A, HAS_F>);
+    int grid = per_cu * device_cus(dev);
+    if ((uint32_t)grid > G.nitems) grid = (int)G.nitems;
+    hipLaunchKernelGGL((gs_wavefront_kernel<T, HAS_A, HAS_F>), dim3(grid), dim3(64), 0, s, G);
     return hipGetLastError();
 }
 
@@ -402,12 +465,111 @@ hipError_t launch_gs_any(const Geom &g, void *u, const void *f, double a, double
     return launch_gs_t<T, false, false>(g, u, f, a, b, gw, S, s, err);
 }
 
+// ---- batched launch (job service) ----
+
+template <typename T, bool HAS_A, bool HAS_F>
+hipError_t launch_gs_batch_t(const std::vector<GsBatchItem> &items, GsBatchWork &w,
+                             hipStream_t s) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const size_t nj_ = items.size();
+    // progress counters: one block per job, [sweeps][bundles]
+    size_t ncount = 0;
+    std::vector<size_t> off(nj_);
+    for (size_t j = 0; j < nj_; ++j) {
+        const int nj = (items[j].g.ny + 7) / 8, nk = (items[j].g.nz + 7) / 8;
+        off[j] = ncount;
+        ncount += (size_t)items[j].sweeps * nj * nk;
+    }
+    // merged item list in key order 2*tau + J + K (ties: by job)
+    w.items.clear();
+    int kmax = 0;
+    for (const auto &it : items) {
+        const int nj = (it.g.ny + 7) / 8, nk = (it.g.nz + 7) / 8;
+        kmax = std::max(kmax, 2 * (it.sweeps - 1) + nj - 1 + nk - 1);
+    }
+    for (int key = 0; key <= kmax; ++key)
+        for (size_t j = 0; j < nj_; ++j) {
+            const int nj = (items[j].g.ny + 7) / 8, nk = (items[j].g.nz + 7) / 8;
+            for (int tau = 0; tau < items[j].sweeps; ++tau) {
+                const int rest = key - 2 * tau;
+                if (rest < 0) break;
+                for (int J = 0; J < nj; ++J) {
+                    const int K = rest - J;
+                    if (K < 0) break;
+                    if (K >= nk) continue;
+                    w.items.push_back(((uint64_t)j << 48) | ((uint64_t)tau << 32) |
+                                      ((uint64_t)J << 16) | (uint64_t)K);
+                }
+            }
+        }
+    const size_t jobs_bytes = nj_ * sizeof(GsJob<T>);
+    const size_t items_bytes = w.items.size() * sizeof(uint64_t);
+    const size_t need = jobs_bytes + items_bytes + ncount * sizeof(uint32_t) + 256 + 512;
+    if (w.dev_bytes < need) {
+        if (w.dev) (void)hipFree(w.dev);
+        w.dev = nullptr;
+        w.dev_bytes = 0;
+        e = hipMalloc(&w.dev, need * 2);
+        if (e != hipSuccess) return e;
+        w.dev_bytes = need * 2;
+    }
+    char *base = static_cast<char *>(w.dev);
+    GsJob<T> *djobs = reinterpret_cast<GsJob<T> *>(base);
+    uint64_t *ditems = reinterpret_cast<uint64_t *>(base + ((jobs_bytes + 255) / 256) * 256);
+    uint32_t *dprog = reinterpret_cast<uint32_t *>(
+        reinterpret_cast<char *>(ditems) + ((items_bytes + 255) / 256) * 256);
+    uint32_t *dticket = dprog + ((ncount + 63) / 64) * 64;
+    w.jobs_host.resize(jobs_bytes);
+    GsJob<T> *hj = reinterpret_cast<GsJob<T> *>(w.jobs_host.data());
+    for (size_t j = 0; j < nj_; ++j)
+        hj[j] = make_job<T>(items[j].g, items[j].u, items[j].f, items[j].a, items[j].b,
+                            items[j].gw, dprog + off[j]);
+    e = hipMemcpyAsync(djobs, hj, jobs_bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(ditems, w.items.data(), items_bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(gs_reset_kernel, dim3(256), dim3(256), 0, s, dprog, (int)ncount, dticket);
+    GsBatchArgs<T> G;
+    G.jobs = djobs;
+    G.nitems = (uint32_t)w.items.size();
+    G.items = ditems;
+    G.ticket = dticket;
+    static int per_cu = 0;
+    if (per_cu == 0) per_cu = per_cu_occupancy(gs_batch_kernel<T, HAS_A, HAS_F>);
+    int grid = per_cu * device_cus(dev);
+    if ((uint32_t)grid > G.nitems) grid = (int)G.nitems;
+    hipLaunchKernelGGL((gs_batch_kernel<T, HAS_A, HAS_F>), dim3(grid), dim3(64), 0, s, G);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gs_batch_any(bool ha, bool hf, const std::vector<GsBatchItem> &items,
+                               GsBatchWork &w, hipStream_t s) {
+    if (ha && hf) return launch_gs_batch_t<T, true, true>(items, w, s);
+    if (ha) return launch_gs_batch_t<T, true, false>(items, w, s);
+    if (hf) return launch_gs_batch_t<T, false, true>(items, w, s);
+    return launch_gs_batch_t<T, false, false>(items, w, s);
+}
+
 }  // namespace
 
 hipError_t launch_gs(bool fp32, const Geom &g, void *u, const void *f, double a, double b,
                      double gw, int sweeps, hipStream_t s, std::string *err) {
     return fp32 ? launch_gs_any<float>(g, u, f, a, b, gw, sweeps, s, err)
                 : launch_gs_any<double>(g, u, f, a, b, gw, sweeps, s, err);
+}
+
+hipError_t launch_gs_batch(bool fp32, bool has_a, bool has_f,
+                           const std::vector<GsBatchItem> &items, GsBatchWork &w, hipStream_t s) {
+    if (items.empty()) return hipSuccess;
+    return fp32 ? launch_gs_batch_any<float>(has_a, has_f, items, w, s)
+                : launch_gs_batch_any<double>(has_a, has_f, items, w, s);
+}
+
+GsBatchWork::~GsBatchWork() {
+    if (dev) (void)hipFree(dev);
 }
 
 }  // namespace stk

@@ -39,6 +39,23 @@ hipError_t launch_jacobi_pass(bool fp32, int tb, const Geom &g, const void *src,
                               const void *f, double a, double b, double gw, int zc,
                               hipStream_t s);
 
+// One grid of a batched pass (job service).
+struct JacBatchItem {
+    Geom g;
+    const void *src;
+    void *dst;
+    const void *f;
+    double a, b, gw;
+};
+size_t jacobi_batch_table_bytes(int njobs);
+// All items share dtype, tb and the presence of the centre / RHS terms.
+// table_dev: device buffer of jacobi_batch_table_bytes(items.size()) bytes;
+// host_buf: staging memory that must stay untouched until the copy is done
+// (the copy is from pageable memory, so it is complete when the call returns).
+hipError_t launch_jacobi_batch(bool fp32, int tb, bool has_a, bool has_f,
+                               const std::vector<JacBatchItem> &items, void *table_dev,
+                               std::vector<unsigned char> &host_buf, hipStream_t s);
+
 // Ghost-layer helpers (all ghost cells of a padded grid).
 hipError_t launch_fill_ghosts(bool fp32, const Geom &g, void *u, double value, hipStream_t s);
 hipError_t launch_copy_ghosts(bool fp32, const Geom &g, const void *src, void *dst,
@@ -61,9 +78,29 @@ int residual_partial_count(const Geom &g);
 hipError_t launch_correct(const Geom &g, double *u, const void *e, bool e_fp32, hipStream_t s);
 
 // Gauss-Seidel wavefront (all sweeps of one launch).
-struct GsPlan;
 hipError_t launch_gs(bool fp32, const Geom &g, void *u, const void *f, double a, double b,
                      double gw, int sweeps, hipStream_t s, std::string *err);
+
+// Batched wavefront (job service): `sweeps` sweeps of every item's grid in
+// one launch; items of all grids share one ticket counter in key order.
+struct GsBatchItem {
+    Geom g;
+    void *u;
+    const void *f;
+    double a, b, gw;
+    int sweeps;
+};
+// Device workspace (job table, item list, counters) owned by the caller;
+// must not be reused before the launch that used it has completed.
+struct GsBatchWork {
+    void *dev = nullptr;
+    size_t dev_bytes = 0;
+    std::vector<uint64_t> items;
+    std::vector<unsigned char> jobs_host;
+    ~GsBatchWork();
+};
+hipError_t launch_gs_batch(bool fp32, bool has_a, bool has_f,
+                           const std::vector<GsBatchItem> &items, GsBatchWork &w, hipStream_t s);
 
 // Thread-local error message used by the C ABI.
 void set_error(const std::string &msg);

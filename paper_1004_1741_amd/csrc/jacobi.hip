@@ -353,6 +353,51 @@ __global__ void __launch_bounds__(NW * 64) jacobi_pass_kernel(JacArgs<T> A) {
         jacobi_tile<T, TB, VX, RY, NW, HAS_A, HAS_F, true>(A, tx, ty, cz, xch);
 }
 
+// Batched pass: one launch advances several independent grids (jobs of the
+// job service) by one fused pass each.  jobs[j].wg_begin is the prefix sum of
+// the workgroups of the jobs before j; a workgroup finds its job by binary
+// search and then runs exactly the single-grid tile code, so a job's result
+// does not depend on which other jobs share the launch.
+template <typename T>
+struct JacJob {
+    JacArgs<T> a;
+    int wg_begin;
+    int pad_[3];
+};
+
+template <typename T, int TB, int VX, int RY, int NW, bool HAS_A, bool HAS_F>
+__global__ void __launch_bounds__(NW * 64)
+    jacobi_batch_kernel(const JacJob<T> *__restrict__ jobs, int njobs, int total) {
+    __shared__ T xch[2][TB][NW][2][64 * VX];
+    const int G = gridDim.x;
+    const int per = G >> 3;
+    const int bid = blockIdx.x;
+    const int l = (bid & 7) * per + (bid >> 3);
+    if (l >= total) return;
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].wg_begin <= l) lo = mid; else hi = mid - 1;
+    }
+    const JacArgs<T> A = jobs[lo].a;
+    const int li = l - jobs[lo].wg_begin;
+    const int tpc = A.tiles_x * A.tiles_y;
+    const int cz = li / tpc;
+    const int rem = li - cz * tpc;
+    const int ty = rem / A.tiles_x;
+    const int tx = rem - ty * A.tiles_x;
+    const int ox0 = A.h + tx * A.ow;
+    int xs = ox0 - TB;
+    xs -= ((xs % VX) + VX) % VX;
+    const int ys = A.h + ty * A.oh - TB;
+    const bool interior = xs >= A.h && xs + 64 * VX <= A.h + A.nx && ys >= A.h &&
+                          ys + NW * RY <= A.h + A.ny;
+    if (interior)
+        jacobi_tile<T, TB, VX, RY, NW, HAS_A, HAS_F, false>(A, tx, ty, cz, xch);
+    else
+        jacobi_tile<T, TB, VX, RY, NW, HAS_A, HAS_F, true>(A, tx, ty, cz, xch);
+}
+
 // Tile configurations.  Register demand per thread is about
 // (2*TB + 3) * RY * VX values; the shapes keep it within 256 VGPRs (two
 // waves per SIMD) while making the tile as large as possible against the
@@ -373,23 +418,54 @@ JacTileCfg cfg_of() {
     return JacTileCfg{TB, Cfg<T, TB>::VX, Cfg<T, TB>::RY, Cfg<T, TB>::NW};
 }
 
-// Number of z-chunks: enough workgroups to fill 256 CUs several times over,
-// but chunks no thinner than 4*TB planes (each chunk re-reads TB planes).
-int choose_chunks(const JacTileCfg &c, const Geom &g, int tiles_xy) {
-    const int target = 2048;
-    int nch = (target + tiles_xy - 1) / tiles_xy;
-    const int minzc = 4 * c.tb > 16 ? 4 * c.tb : 16;
-    int maxch = g.nz / minzc;
-    if (maxch < 1) maxch = 1;
-    if (nch > maxch) nch = maxch;
-    if (nch < 1) nch = 1;
-    return nch;
+// Number of z-chunks.  Every chunk re-computes TB warm-up planes (and some
+// fill/drain steps), while the grid runs in rounds of `resident` workgroups:
+// pick the count that minimises rounds * (planes per chunk + fill).
+int choose_chunks(const JacTileCfg &c, const Geom &g, int tiles_xy, int resident) {
+    if (resident < 1) resident = 256;
+    int best = 1;
+    double best_cost = 1e300;
+    const int maxch = g.nz / 8 > 1 ? g.nz / 8 : 1;
+    for (int nch = 1; nch <= maxch; ++nch) {
+        const int zc = (g.nz + nch - 1) / nch;
+        const long wgs = (long)tiles_xy * nch;
+        const long rounds = (wgs + resident - 1) / resident;
+        const double cost = (double)rounds * (zc + c.tb + 1);
+        if (cost < best_cost - 1e-9) {
+            best_cost = cost;
+            best = nch;
+        }
+    }
+    return best;
 }
 
 template <typename T, int TB, bool HAS_A, bool HAS_F>
-hipError_t launch_t(const Geom &g, const void *src, void *dst, const void *f, double a, double b,
-                    double gw, int zc, hipStream_t s) {
+int resident_wgs(bool batch) {
     using C = Cfg<T, TB>;
+    static int cached[2] = {0, 0};
+    int &r = cached[batch ? 1 : 0];
+    if (r == 0) {
+        int per_cu = 0, dev = 0, ncu = 0;
+        const void *kfn =
+            batch ? reinterpret_cast<const void *>(
+                        jacobi_batch_kernel<T, TB, C::VX, C::RY, C::NW, HAS_A, HAS_F>)
+                  : reinterpret_cast<const void *>(
+                        jacobi_pass_kernel<T, TB, C::VX, C::RY, C::NW, HAS_A, HAS_F>);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, C::NW * 64, 0) !=
+                hipSuccess || per_cu < 1)
+            per_cu = 1;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) !=
+                hipSuccess || ncu < 1)
+            ncu = 256;
+        r = per_cu * ncu;
+    }
+    return r;
+}
+
+template <typename T, int TB>
+JacArgs<T> make_args(const Geom &g, const void *src, void *dst, const void *f, double a,
+                     double b, double gw, int zc, int resident) {
     const JacTileCfg c = cfg_of<T, TB>();
     JacArgs<T> A;
     A.src = static_cast<const T *>(src);
@@ -405,16 +481,70 @@ hipError_t launch_t(const Geom &g, const void *src, void *dst, const void *f, do
     A.tiles_y = (g.ny + A.oh - 1) / A.oh;
     const int tiles_xy = A.tiles_x * A.tiles_y;
     if (zc <= 0) {
-        const int nch = choose_chunks(c, g, tiles_xy);
+        const int nch = choose_chunks(c, g, tiles_xy, resident);
         zc = (g.nz + nch - 1) / nch;
     }
     A.zc = zc;
     A.nchunks = (g.nz + zc - 1) / zc;
     A.ntiles = tiles_xy * A.nchunks;
+    return A;
+}
+
+template <typename T, int TB, bool HAS_A, bool HAS_F>
+hipError_t launch_t(const Geom &g, const void *src, void *dst, const void *f, double a, double b,
+                    double gw, int zc, hipStream_t s) {
+    using C = Cfg<T, TB>;
+    const JacArgs<T> A = make_args<T, TB>(g, src, dst, f, a, b, gw, zc,
+                                          resident_wgs<T, TB, HAS_A, HAS_F>(false));
     const int grid = ((A.ntiles + 7) / 8) * 8;
     hipLaunchKernelGGL((jacobi_pass_kernel<T, TB, C::VX, C::RY, C::NW, HAS_A, HAS_F>),
                        dim3(grid), dim3(C::NW * 64), 0, s, A);
     return hipGetLastError();
+}
+
+template <typename T, int TB, bool HAS_A, bool HAS_F>
+hipError_t launch_batch_t(const std::vector<JacBatchItem> &items, void *table_dev,
+                          std::vector<unsigned char> &host_buf, hipStream_t s) {
+    using C = Cfg<T, TB>;
+    const int resident = resident_wgs<T, TB, HAS_A, HAS_F>(true);
+    host_buf.resize(items.size() * sizeof(JacJob<T>));
+    JacJob<T> *jobs = reinterpret_cast<JacJob<T> *>(host_buf.data());
+    int total = 0;
+    for (size_t j = 0; j < items.size(); ++j) {
+        const JacBatchItem &it = items[j];
+        jobs[j].a = make_args<T, TB>(it.g, it.src, it.dst, it.f, it.a, it.b, it.gw, 0, resident);
+        jobs[j].wg_begin = total;
+        total += jobs[j].a.ntiles;
+    }
+    hipError_t e = hipMemcpyAsync(table_dev, jobs, items.size() * sizeof(JacJob<T>),
+                                  hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    const int grid = ((total + 7) / 8) * 8;
+    hipLaunchKernelGGL((jacobi_batch_kernel<T, TB, C::VX, C::RY, C::NW, HAS_A, HAS_F>),
+                       dim3(grid), dim3(C::NW * 64), 0, s,
+                       static_cast<const JacJob<T> *>(table_dev), (int)items.size(), total);
+    return hipGetLastError();
+}
+
+template <typename T, int TB>
+hipError_t launch_batch_tb(bool ha, bool hf, const std::vector<JacBatchItem> &items,
+                           void *table_dev, std::vector<unsigned char> &hb, hipStream_t s) {
+    if (ha && hf) return launch_batch_t<T, TB, true, true>(items, table_dev, hb, s);
+    if (ha) return launch_batch_t<T, TB, true, false>(items, table_dev, hb, s);
+    if (hf) return launch_batch_t<T, TB, false, true>(items, table_dev, hb, s);
+    return launch_batch_t<T, TB, false, false>(items, table_dev, hb, s);
+}
+
+template <typename T>
+hipError_t launch_batch_any(int tb, bool ha, bool hf, const std::vector<JacBatchItem> &items,
+                            void *table_dev, std::vector<unsigned char> &hb, hipStream_t s) {
+    switch (tb) {
+        case 1: return launch_batch_tb<T, 1>(ha, hf, items, table_dev, hb, s);
+        case 2: return launch_batch_tb<T, 2>(ha, hf, items, table_dev, hb, s);
+        case 4: return launch_batch_tb<T, 4>(ha, hf, items, table_dev, hb, s);
+        case 8: return launch_batch_tb<T, 8>(ha, hf, items, table_dev, hb, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <typename T, int TB>
@@ -463,6 +593,19 @@ hipError_t launch_jacobi_pass(bool fp32, int tb, const Geom &g, const void *src,
                               hipStream_t s) {
     return fp32 ? launch_any<float>(tb, g, src, dst, f, a, b, gw, zc, s)
                 : launch_any<double>(tb, g, src, dst, f, a, b, gw, zc, s);
+}
+
+size_t jacobi_batch_table_bytes(int njobs) {
+    return (size_t)njobs * (sizeof(JacJob<double>) > sizeof(JacJob<float>) ? sizeof(JacJob<double>)
+                                                                           : sizeof(JacJob<float>));
+}
+
+hipError_t launch_jacobi_batch(bool fp32, int tb, bool has_a, bool has_f,
+                               const std::vector<JacBatchItem> &items, void *table_dev,
+                               std::vector<unsigned char> &host_buf, hipStream_t s) {
+    if (items.empty()) return hipSuccess;
+    return fp32 ? launch_batch_any<float>(tb, has_a, has_f, items, table_dev, host_buf, s)
+                : launch_batch_any<double>(tb, has_a, has_f, items, table_dev, host_buf, s);
 }
 
 }  // namespace stk
