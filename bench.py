@@ -33,6 +33,16 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+def bytes_per_lup(elem_bytes: int, t: int) -> float:
+    """Eq. (1): one load and one store per site per pass of t fused sweeps."""
+    return 2.0 * elem_bytes / t
+
+
+def eq1_mlups(bandwidth_GBs: float, elem_bytes: int = 8, t: int = 1) -> float:
+    """Bandwidth-bound lattice-site updates per second, Eq. (1), in MLUP/s."""
+    return bandwidth_GBs * 1e9 / bytes_per_lup(elem_bytes, t) / 1e6
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -143,7 +153,8 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
             "kernel": "jacobi_pass_kernel<double,t=%d>" % max(plan),
             "pass_us": round(pass_ms * 1e3, 2), "bytes_per_pass": pass_bytes,
-            "bytes_per_lup": round(16.0 / (S / passes), 3)}
+            "bytes_per_lup": round(bytes_per_lup(8, S / passes), 3),
+            "roofline_MLUPs_at_peak": round(eq1_mlups(HBM_PEAK_GBS, 8, S / passes))}
 
     extra = {}
     if not args.quick:

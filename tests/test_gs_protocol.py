@@ -1,0 +1,29 @@
+"""The Gauss-Seidel wavefront protocol, emulated on the CPU (no GPU)."""
+import numpy as np
+import pytest
+
+import gs_protocol_model as M
+import oracle
+import synthetic_inputs as si
+
+
+@pytest.mark.parametrize("dims,S,workers,seed", [
+    ((9, 8, 8), 2, 2, 0), ((5, 9, 17), 3, 3, 1), ((1, 1, 1), 2, 2, 3), ((16, 16, 9), 4, 1, 4),
+    ((24, 11, 19), 2, 7, 5), ((100, 30, 9), 5, 16, 2),
+])
+def test_protocol_matches_sequential_sweeps(dims, S, workers, seed):
+    nx, ny, nz = dims
+    u0 = si.uniform_padded(nx, ny, nz, 1, seed=seed, lo=-1.0, hi=1.0)
+    got = M.simulate(u0, S, workers=workers, seed=seed)
+    assert np.array_equal(got, oracle.gauss_seidel(u0, S))
+
+
+def test_ticket_order_is_topological():
+    items = M.items_table(5, 4, 6)
+    pos = {it: n for n, it in enumerate(items)}
+    assert len(pos) == 5 * 4 * 6
+    for (tau, J, K), n in pos.items():
+        for d in ((tau, J - 1, K), (tau, J, K - 1), (tau - 1, J + 1, K), (tau - 1, J, K + 1),
+                  (tau - 1, J, K)):
+            if d in pos:
+                assert pos[d] < n
