@@ -43,6 +43,27 @@ def eq1_mlups(bandwidth_GBs: float, elem_bytes: int = 8, t: int = 1) -> float:
     return bandwidth_GBs * 1e9 / bytes_per_lup(elem_bytes, t) / 1e6
 
 
+def measured_traffic(kernel_t, n):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, each scaled by the
+    plain-copy calibration), or None if that summary does not describe the
+    kernel as it is now built (source changed) or this workload."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", "jacobi_pass_fp64_t4_512cubed.md")
+    src = os.path.join(ROOT, "paper_1004_1741_amd", "csrc", "jacobi.hip")
+    if kernel_t != 4 or n != 512 or not os.path.exists(prof):
+        return None
+    vals = {}
+    for line in open(prof):
+        if " = " in line:
+            k, v = line.strip().split(" = ", 1)
+            vals[k] = v
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if vals.get("kernel_source_sha256_16") != sha:
+        return None
+    return float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"])
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -60,6 +81,8 @@ def parse():
     ap.add_argument("--poisson-n", type=int, default=256)
     ap.add_argument("--serving-jobs", type=int, default=300)
     ap.add_argument("--serving-rate", type=float, default=200.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one 2 GiB device copy (counter calibration)")
     return ap.parse_args()
 
 
@@ -112,6 +135,88 @@ def cpu_baseline(n, target_s=12.0):
                       "C oracle, %.1f s" % (n, S, dt)}
 
 
+def poisson_compare(P, torch, n, seed=0, methods=(0, 1), m=32, tol=1e-10):
+    """-Laplace u = f on n^3, h = 1/(n+1), f U[-1,1), u0 = 0: time to reach
+    ||f' - A u|| <= tol ||f'|| with the FP32-refined loop and the plain FP64 method."""
+    import synthetic_inputs as si
+    w = si.poisson(n=n, seed=seed)
+    fp = torch.from_numpy(w["f"] / float((n + 1) ** 2)).to("cuda")
+    out = {}
+    for method in methods:
+        name = "jacobi" if method == 0 else "gauss_seidel"
+        res = {}
+        for inner_fp32, key in ((True, "fp32_refined"), (False, "plain_fp64")):
+            u = torch.from_numpy(w["u"]).to("cuda")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rounds, rel, rc = P.refine_solve(u, fp, method=method, inner_fp32=inner_fp32,
+                                             inner_sweeps=m, rel_tol=tol, max_outer=10 ** 7,
+                                             raise_on_noconv=False)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            sweeps = rounds * m
+            res[key] = {"seconds": round(dt, 3), "outer_rounds": rounds, "sweeps": sweeps,
+                        "rel_residual": rel, "status": rc,
+                        "MLUPs": round(float(n) ** 3 * sweeps / dt / 1e6)}
+            res[key + "_u"] = u
+            log("poisson %d^3 %s %s: %s" % (n, name, key, {k: v for k, v in res[key].items()}))
+        a, b = res.pop("fp32_refined_u"), res.pop("plain_fp64_u")
+        res["rel_diff_fp32_refined_vs_fp64"] = float((a - b).abs().max() / b.abs().max())
+        res["speedup_fp32_refined"] = round(res["plain_fp64"]["seconds"] /
+                                            res["fp32_refined"]["seconds"], 3)
+        out[name] = res
+        del a, b
+    return out
+
+
+def serving_stream(P, n_jobs, rate, seed=0, budget=32 << 30, max_inflight=64):
+    """Continuous-batching service under a Poisson arrival stream of uneven
+    jobs (extents U{32..256}, Jacobi/GS and FP64/FP32-refined 50/50, 2..20
+    sweeps).  Inputs are generated before the clock starts."""
+    import threading
+    import synthetic_inputs as si
+    jobs = si.serving_stream(n_jobs=n_jobs, rate_per_s=rate, seed=seed)
+    inputs = [j.make_input() for j in jobs]
+    outputs = [np.empty_like(x) for x in inputs]
+    svc = P.SmoothService(budget, max_inflight=max_inflight)
+    ids = [None] * n_jobs
+    t0 = time.perf_counter()
+
+    def feeder():
+        for k, j in enumerate(jobs):
+            dt = j.arrival_s - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            ids[k] = svc.submit(inputs[k], outputs[k], j.sweeps, method=j.method,
+                                precision=j.precision)
+
+    th = threading.Thread(target=feeder)
+    th.start()
+    th.join()
+    svc.wait_all()
+    wall = time.perf_counter() - t0
+    lat, queue, run, lups = [], [], [], 0.0
+    for k in range(n_jobs):
+        st, stats = svc.poll(ids[k])
+        assert st == P.SmoothService.DONE
+        lat.append((stats.t_done_ns - stats.t_submit_ns) * 1e-6)
+        queue.append((stats.t_admit_ns - stats.t_submit_ns) * 1e-6)
+        run.append((stats.t_done_ns - stats.t_start_ns) * 1e-6)
+        lups += stats.lups
+    info = svc.info()
+    svc.shutdown()
+    lat = np.array(lat)
+    return {"jobs": n_jobs, "rate_per_s": rate, "wall_s": round(wall, 3),
+            "p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "mean_queue_ms": round(float(np.mean(queue)), 3),
+            "mean_start_to_done_ms": round(float(np.mean(run)), 3),
+            "MLUPs_aggregate": round(lups / wall / 1e6),
+            "batches": info.batches, "max_resident": info.max_resident_seen,
+            "footprint_high_water_GB": round(info.footprint_high_water / 1e9, 3),
+            "budget_GB": round(budget / 1e9, 3)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -145,16 +250,31 @@ def main():
     value = lups_step / (ms_step * 1e-3) / 1e6
     log("headline: %.3f ms/step, %.0f MLUP/s, plan %s" % (ms_step, value, plan))
 
-    # dominant kernel: the fused pass; its average launch duration from the same events
-    pass_ms = ms_step / passes
+    # Dominant kernel: the fused pass of depth tdom.  Its average launch
+    # duration is measured with HIP events over launches of that kernel only
+    # (a schedule of 2*k passes of depth tdom), on the stream it runs on.
+    tdom = max(plan)
+    k = 12
+    jacobi_run(P, torch, u, s, 2 * k * tdom, tdom)
+    dom_ms = events_time(torch, lambda: jacobi_run(P, torch, u, s, 2 * k * tdom, tdom),
+                         reps=2) / (2 * 2 * k)
     pass_bytes = 2 * 8 * float(n) ** 3
-    achieved = pass_bytes / (pass_ms * 1e-3) / 1e9
+    achieved = pass_bytes / (dom_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "jacobi_pass_kernel<double,t=%d>" % max(plan),
-            "pass_us": round(pass_ms * 1e3, 2), "bytes_per_pass": pass_bytes,
-            "bytes_per_lup": round(bytes_per_lup(8, S / passes), 3),
-            "roofline_MLUPs_at_peak": round(eq1_mlups(HBM_PEAK_GBS, 8, S / passes))}
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(tdom, n),
+            "traffic_unit": "bytes/launch (rocprofv3 FETCH_SIZE+WRITE_SIZE, copy-calibrated)",
+            "kernel": "jacobi_pass_kernel<double,t=%d>" % tdom,
+            "launch_us": round(dom_ms * 1e3, 2), "algorithmic_bytes_per_launch": pass_bytes,
+            "bytes_per_lup": round(bytes_per_lup(8, tdom), 3),
+            "sweeps_per_launch": tdom,
+            "roofline_MLUPs_at_peak": round(eq1_mlups(HBM_PEAK_GBS, 8, tdom))}
+    log("dominant kernel t=%d: %.1f us/launch, %.1f GB/s" % (tdom, dom_ms * 1e3, achieved))
+    if args.copy_probe:
+        a = torch.empty(1 << 28, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     extra = {}
     if not args.quick:
@@ -202,6 +322,14 @@ def main():
         extra["gs_384_x50"] = gs
         del ug, u0
         torch.cuda.synchronize()
+        # free the 512^3 grids before the remaining measurements
+        del u, s
+        torch.cuda.empty_cache()
+        if args.poisson_n > 0:
+            extra["poisson_%d" % args.poisson_n] = poisson_compare(P, torch, args.poisson_n)
+        if args.serving_jobs > 0:
+            extra["serving"] = serving_stream(P, args.serving_jobs, args.serving_rate)
+            log("serving: %s" % extra["serving"])
 
     line = {
         "metric": "MLUP/s & HBM-roofline fraction at 512^3 (FP64 vs FP32-refined); job p50/p99",
