@@ -61,7 +61,7 @@ int check_grid(const st_grid *g, Geom *out) {
 
 bool valid_t(int t) { return t == 0 || t == 1 || t == 2 || t == 4 || t == 8 || t == 16; }
 
-int auto_t(int dtype) { return dtype == ST_FP32 ? 4 : 4; }
+int auto_t(int dtype) { return dtype == ST_FP32 ? 8 : 4; }
 
 // Pass schedule: floor(S/t) passes of t plus the binary decomposition of the
 // remainder; if the count is odd the smallest pass with >= 2 sweeps is split

@@ -398,24 +398,30 @@ __global__ void __launch_bounds__(NW * 64)
         jacobi_tile<T, TB, VX, RY, NW, HAS_A, HAS_F, true>(A, tx, ty, cz, xch);
 }
 
-// Tile configurations.  Register demand per thread is about
-// (2*TB + 3) * RY * VX values; the shapes keep it within 256 VGPRs (two
-// waves per SIMD) while making the tile as large as possible against the
-// 2*TB overlap.
+// Tile configurations (VX, RY, NW), chosen by measurement on MI355X among
+// shapes that fit the register file: per thread about (2*TB + 3) * RY * VX
+// values stay live, which must fit 256 VGPRs (two waves per SIMD), while the
+// tile must be large against the 2*TB overlap on each side.
 template <typename T, int TB>
-struct Cfg;
-template <> struct Cfg<double, 1> { static constexpr int VX = 2, RY = 4, NW = 8; };
-template <> struct Cfg<double, 2> { static constexpr int VX = 2, RY = 4, NW = 8; };
-template <> struct Cfg<double, 4> { static constexpr int VX = 2, RY = 4, NW = 8; };
-template <> struct Cfg<double, 8> { static constexpr int VX = 1, RY = 6, NW = 8; };
-template <> struct Cfg<float, 1> { static constexpr int VX = 4, RY = 4, NW = 8; };
-template <> struct Cfg<float, 2> { static constexpr int VX = 4, RY = 4, NW = 8; };
-template <> struct Cfg<float, 4> { static constexpr int VX = 4, RY = 4, NW = 8; };
-template <> struct Cfg<float, 8> { static constexpr int VX = 2, RY = 6, NW = 8; };
+struct CfgBase;
+template <> struct CfgBase<double, 1> { static constexpr int VX = 2, RY = 4, NW = 8; };
+template <> struct CfgBase<double, 2> { static constexpr int VX = 2, RY = 4, NW = 8; };
+template <> struct CfgBase<double, 4> { static constexpr int VX = 1, RY = 8, NW = 8; };
+template <> struct CfgBase<double, 8> { static constexpr int VX = 1, RY = 5, NW = 8; };
+template <> struct CfgBase<float, 1> { static constexpr int VX = 2, RY = 8, NW = 8; };
+template <> struct CfgBase<float, 2> { static constexpr int VX = 2, RY = 8, NW = 8; };
+template <> struct CfgBase<float, 4> { static constexpr int VX = 2, RY = 6, NW = 8; };
+template <> struct CfgBase<float, 8> { static constexpr int VX = 1, RY = 8, NW = 8; };
+// With a right-hand side the f values of each level add register pressure:
+// the deepest FP64 shapes would spill, so they use shallower tiles.
+template <typename T, int TB, bool HAS_F>
+struct Cfg : CfgBase<T, TB> {};
+template <> struct Cfg<double, 4, true> { static constexpr int VX = 1, RY = 6, NW = 8; };
+template <> struct Cfg<double, 8, true> { static constexpr int VX = 1, RY = 4, NW = 8; };
 
-template <typename T, int TB>
+template <typename T, int TB, bool HAS_F = false>
 JacTileCfg cfg_of() {
-    return JacTileCfg{TB, Cfg<T, TB>::VX, Cfg<T, TB>::RY, Cfg<T, TB>::NW};
+    return JacTileCfg{TB, Cfg<T, TB, HAS_F>::VX, Cfg<T, TB, HAS_F>::RY, Cfg<T, TB, HAS_F>::NW};
 }
 
 // Number of z-chunks.  Every chunk re-computes TB warm-up planes (and some
@@ -441,7 +447,7 @@ int choose_chunks(const JacTileCfg &c, const Geom &g, int tiles_xy, int resident
 
 template <typename T, int TB, bool HAS_A, bool HAS_F>
 int resident_wgs(bool batch) {
-    using C = Cfg<T, TB>;
+    using C = Cfg<T, TB, HAS_F>;
     static int cached[2] = {0, 0};
     int &r = cached[batch ? 1 : 0];
     if (r == 0) {
@@ -463,10 +469,10 @@ int resident_wgs(bool batch) {
     return r;
 }
 
-template <typename T, int TB>
+template <typename T, int TB, bool HAS_F>
 JacArgs<T> make_args(const Geom &g, const void *src, void *dst, const void *f, double a,
                      double b, double gw, int zc, int resident) {
-    const JacTileCfg c = cfg_of<T, TB>();
+    const JacTileCfg c = cfg_of<T, TB, HAS_F>();
     JacArgs<T> A;
     A.src = static_cast<const T *>(src);
     A.dst = static_cast<T *>(dst);
@@ -493,8 +499,8 @@ JacArgs<T> make_args(const Geom &g, const void *src, void *dst, const void *f, d
 template <typename T, int TB, bool HAS_A, bool HAS_F>
 hipError_t launch_t(const Geom &g, const void *src, void *dst, const void *f, double a, double b,
                     double gw, int zc, hipStream_t s) {
-    using C = Cfg<T, TB>;
-    const JacArgs<T> A = make_args<T, TB>(g, src, dst, f, a, b, gw, zc,
+    using C = Cfg<T, TB, HAS_F>;
+    const JacArgs<T> A = make_args<T, TB, HAS_F>(g, src, dst, f, a, b, gw, zc,
                                           resident_wgs<T, TB, HAS_A, HAS_F>(false));
     const int grid = ((A.ntiles + 7) / 8) * 8;
     hipLaunchKernelGGL((jacobi_pass_kernel<T, TB, C::VX, C::RY, C::NW, HAS_A, HAS_F>),
@@ -505,14 +511,14 @@ hipError_t launch_t(const Geom &g, const void *src, void *dst, const void *f, do
 template <typename T, int TB, bool HAS_A, bool HAS_F>
 hipError_t launch_batch_t(const std::vector<JacBatchItem> &items, void *table_dev,
                           std::vector<unsigned char> &host_buf, hipStream_t s) {
-    using C = Cfg<T, TB>;
+    using C = Cfg<T, TB, HAS_F>;
     const int resident = resident_wgs<T, TB, HAS_A, HAS_F>(true);
     host_buf.resize(items.size() * sizeof(JacJob<T>));
     JacJob<T> *jobs = reinterpret_cast<JacJob<T> *>(host_buf.data());
     int total = 0;
     for (size_t j = 0; j < items.size(); ++j) {
         const JacBatchItem &it = items[j];
-        jobs[j].a = make_args<T, TB>(it.g, it.src, it.dst, it.f, it.a, it.b, it.gw, 0, resident);
+        jobs[j].a = make_args<T, TB, HAS_F>(it.g, it.src, it.dst, it.f, it.a, it.b, it.gw, 0, resident);
         jobs[j].wg_begin = total;
         total += jobs[j].a.ntiles;
     }

@@ -129,7 +129,7 @@ def test_jacobi_plan(P, fp32):
         for t in (0, 1, 2, 4, 8, 16):
             plan, fc = P.jacobi_plan(S, t, fp32=fp32)
             assert sum(plan) == S
-            tmax = {0: 4, 16: 8}.get(t, t)
+            tmax = {0: (8 if fp32 else 4), 16: 8}.get(t, t)
             assert all(p in (1, 2, 4, 8) and p <= tmax for p in plan)
             if fc:
                 assert len(plan) % 2 == 1 and all(p == 1 for p in plan)
