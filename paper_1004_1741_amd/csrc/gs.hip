@@ -163,49 +163,71 @@ __device__ __forceinline__ void gs_item(const GsJob<T> &A, int tau, int J, int K
         }
         const int xoff = lane & 7;  // position within a chunk of every element
 
+        // Dependencies: own bundle at tau-1, (J+1,K) and (J,K+1) at tau-1 (old
+        // values), (J-1,K) and (J,K-1) at tau (fresh values).  The five polls
+        // of one chunk are issued together and only the unsatisfied ones spin.
+        // (Carrying the last seen values from chunk to chunk keeps five more
+        // registers live through the sweep and measured markedly slower.)
+        const uint32_t *dep[5] = {Pprev + me, Pprev + me + 1, Pprev + me + A.nj, Pcur + me - 1,
+                                  Pcur + me - A.nj};
+        const bool has[5] = {tau > 0, tau > 0 && J + 1 < A.nj, tau > 0 && K + 1 < A.nk, J > 0,
+                             K > 0};
         auto wait_chunk = [&](int c) {
             if (c * GS_C >= A.nx) return;  // only the x+ ghost column: never written
             const uint32_t need = (uint32_t)c + 1u;
-            if (tau > 0) {
-                wait_at_least(Pprev + me, need);                         // own lines, old
-                if (J + 1 < A.nj) wait_at_least(Pprev + me + 1, need);    // y+ halo, old
-                if (K + 1 < A.nk) wait_at_least(Pprev + me + A.nj, need); // z+ halo, old
-            }
-            if (J > 0) wait_at_least(Pcur + me - 1, need);                // y- halo, new
-            if (K > 0) wait_at_least(Pcur + me - A.nj, need);             // z- halo, new
-            // keep the coherent data loads below after the counter polls
+            uint32_t v[5];
+#pragma unroll
+            for (int q = 0; q < 5; ++q)
+                v[q] = has[q] ? __hip_atomic_load(dep[q], __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT)
+                              : need;
+#pragma unroll
+            for (int q = 0; q < 5; ++q)
+                while (v[q] < need) {
+                    __builtin_amdgcn_s_sleep(2);
+                    v[q] = __hip_atomic_load(dep[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            // keep the coherent data loads below after the counter checks
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         };
-        auto load_chunk = [&](int c) {
+        // Chunk staging is software-pipelined: the global loads of chunk c are
+        // issued one block before c is written to LDS, and the stores of a
+        // finished chunk are published one block after they were issued, so
+        // neither latency stalls the sweep.
+        T pf[12];  // chunk in flight from global memory
+        T fpf[HAS_F ? 8 : 1];
+        auto issue_load = [&](int c) {
             const int i = c * GS_C + xoff;
             const bool iok = i <= A.nx;
-            const int r = i & (GS_RING - 1);
-            T v[12];
 #pragma unroll
             for (int m = 0; m < 12; ++m)
-                v[m] = (iok && lok[m]) ? coherent_load(lsrc[m] + c * GS_C) : T(0);
-#pragma unroll
-            for (int m = 0; m < 12; ++m) ring[lring[m] + r] = v[m];
+                pf[m] = (iok && lok[m]) ? coherent_load(lsrc[m] + c * GS_C) : T(0);
             if constexpr (HAS_F) {
-                T fv[8];
 #pragma unroll
                 for (int m = 0; m < 8; ++m) {
                     const int e = lane + 64 * m;
                     const int li = e >> 3;
                     const int jq = li & 7, kq = li >> 3;
                     const int jg = j0 + jq, kg = k0 + kq;
-                    fv[m] = (i < A.nx && sok[m])
-                                ? A.f[((int64_t)(kg - h) * A.ny + (jg - h)) * A.nx + i]
-                                : T(0);
-                }
-#pragma unroll
-                for (int m = 0; m < 8; ++m) {
-                    const int li = (lane + 64 * m) >> 3;
-                    fring[((li >> 3) * 10 + (li & 7)) * GS_S + r] = fv[m];
+                    fpf[m] = (i < A.nx && sok[m])
+                                 ? A.f[((int64_t)(kg - h) * A.ny + (jg - h)) * A.nx + i]
+                                 : T(0);
                 }
             }
         };
-        auto store_chunk = [&](int c) {
+        auto commit_load = [&](int c) {  // prefetched chunk -> LDS ring
+            const int r = (c * GS_C + xoff) & (GS_RING - 1);
+#pragma unroll
+            for (int m = 0; m < 12; ++m) ring[lring[m] + r] = pf[m];
+            if constexpr (HAS_F) {
+#pragma unroll
+                for (int m = 0; m < 8; ++m) {
+                    const int li = (lane + 64 * m) >> 3;
+                    fring[((li >> 3) * 10 + (li & 7)) * GS_S + r] = fpf[m];
+                }
+            }
+        };
+        auto issue_store = [&](int c) {  // LDS ring -> global (not yet published)
             const int i = c * GS_C + xoff;
             const int r = i & (GS_RING - 1);
             T v[8];
@@ -216,7 +238,8 @@ __device__ __forceinline__ void gs_item(const GsJob<T> &A, int tau, int J, int K
                 for (int m = 0; m < 8; ++m)
                     if (sok[m]) coherent_store(sdst[m] + c * GS_C, v[m]);
             }
-            wait_vm_done();  // the chunk's stores are complete before it is published
+        };
+        auto publish = [&](int c) {  // stores of chunk c have completed
             if (lane == 0)
                 __hip_atomic_store(Pcur + me, (uint32_t)c + 1u, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
@@ -226,11 +249,18 @@ __device__ __forceinline__ void gs_item(const GsJob<T> &A, int tau, int J, int K
         T xm = T(0);
         if (active) xm = A.u[(int64_t)k * A.plane + (int64_t)j * A.px + (h - 1)];
 
+        // prologue: chunks 0 and 1 in LDS, chunk 2 in flight
         wait_chunk(0);
-        load_chunk(0);
+        issue_load(0);
+        commit_load(0);
         if (A.ncl > 1) {
             wait_chunk(1);
-            load_chunk(1);
+            issue_load(1);
+            commit_load(1);
+        }
+        if (A.ncl > 2) {
+            wait_chunk(2);
+            issue_load(2);
         }
         for (int b = 0; b < A.nb; ++b) {
 #pragma unroll
@@ -261,15 +291,25 @@ __device__ __forceinline__ void gs_item(const GsJob<T> &A, int tau, int J, int K
                 // compiler from moving this step's write after the next reads
                 __builtin_amdgcn_wave_barrier();
             }
-            const int cs = b - 2;  // the trailing lane (skew 14) has finished it
-            if (cs >= 0 && cs < A.ncs) store_chunk(cs);
-            const int cl = b + 2;
-            if (cl < A.ncl) {
-                wait_chunk(cl);
-                load_chunk(cl);
+            // block boundary.  Chunk b-2 is final (the trailing lane, skew 14,
+            // is past it); chunk b+2 must be in LDS before block b+1.
+            wait_vm_done();                       // stores of b-3, loads of b+2
+            if (b - 3 >= 0 && b - 3 < A.ncs) publish(b - 3);
+            if (b - 2 >= 0 && b - 2 < A.ncs) issue_store(b - 2);  // reads slot of b+2 first
+            if (b + 2 < A.ncl) commit_load(b + 2);
+            if (b + 3 < A.ncl) {
+                wait_chunk(b + 3);
+                issue_load(b + 3);
             }
         }
-        for (int cs = max(0, A.nb - 2); cs < A.ncs; ++cs) store_chunk(cs);
+        // drain: publish the last issued stores, then store the rest
+        wait_vm_done();
+        if (A.nb - 3 >= 0 && A.nb - 3 < A.ncs) publish(A.nb - 3);
+        for (int cs = max(0, A.nb - 2); cs < A.ncs; ++cs) {
+            issue_store(cs);
+            wait_vm_done();
+            publish(cs);
+        }
 }
 
 template <typename T, bool HAS_A, bool HAS_F>

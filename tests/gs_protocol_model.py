@@ -76,23 +76,32 @@ def simulate(u0, S, h=1, workers=3, seed=0, a=0.0, b=1/6):
                 for (q0, q1) in conds:
                     while P[q0, q1] < c + 1:
                         yield "wait"
-            def load_chunk(c):
+            pf = {}
+            def issue_load(c):  # global -> registers (values read now)
+                vals = []
                 for e in range(768):
                     li = e >> 3; i = c*C + (e & 7)
                     slot = staged_slot(li); jl, kl = slot % 10, slot // 10
                     jg, kg = j0-1+jl, k0-1+kl
                     ok = i <= nx and jg <= h+ny and kg <= h+nz
-                    ring[slot, i & (RING-1)] = u[kg, jg, h+i] if ok else 0.0
-            def store_chunk(c):
+                    vals.append((slot, i & (RING-1), u[kg, jg, h+i] if ok else 0.0))
+                pf["c"] = vals
+            def commit_load(c):  # registers -> LDS ring
+                for slot, r, v in pf["c"]:
+                    ring[slot, r] = v
+            def issue_store(c):  # LDS -> global, not yet published
                 for e in range(512):
                     li = e >> 3; i = c*C + (e & 7); jq, kq = li & 7, li >> 3
                     jg, kg = j0+jq, k0+kq
                     if i < nx and jg < h+ny and kg < h+nz:
                         u[kg, jg, h+i] = ring[(kq+1)*10 + jq+1, i & (RING-1)]
+            def publish(c):
                 P[tau, me] = c + 1
-            yield from wait_chunk(0); load_chunk(0)
+            yield from wait_chunk(0); issue_load(0); commit_load(0)
             if ncl > 1:
-                yield from wait_chunk(1); load_chunk(1)
+                yield from wait_chunk(1); issue_load(1); commit_load(1)
+            if ncl > 2:
+                yield from wait_chunk(2); issue_load(2)
             for bb in range(nb):
                 for st in range(C):
                     T = bb*C + st
@@ -110,12 +119,15 @@ def simulate(u0, S, h=1, workers=3, seed=0, a=0.0, b=1/6):
                     for own, p, v, l in writes:
                         ring[own, p] = v; xm[l] = v
                     yield "step"
-                cs = bb - 2
-                if 0 <= cs < ncs: store_chunk(cs)
-                cl = bb + 2
-                if cl < ncl:
-                    yield from wait_chunk(cl); load_chunk(cl)
-            for cs in range(max(0, nb-2), ncs): store_chunk(cs)
+                if 0 <= bb-3 < ncs: publish(bb-3)
+                yield "boundary"
+                if 0 <= bb-2 < ncs: issue_store(bb-2)
+                if bb+2 < ncl: commit_load(bb+2)
+                if bb+3 < ncl:
+                    yield from wait_chunk(bb+3); issue_load(bb+3)
+            if 0 <= nb-3 < ncs: publish(nb-3)
+            for cs in range(max(0, nb-2), ncs):
+                issue_store(cs); publish(cs)
     rng = random.Random(seed)
     ws = [worker() for _ in range(workers)]
     stall = 0
