@@ -52,24 +52,20 @@ struct VecT<float, 2> {
     typedef float type __attribute__((ext_vector_type(2), aligned(4)));
 };
 
-// Value held by lane l-1 (lane 0 receives 0): DPP wave_shr:1.
 __device__ __forceinline__ float from_lower_lane(float v) {
-    return __int_as_float(
-        __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xf, 0xf, true));
 }
-// Value held by lane l+1 (lane 63 receives 0): DPP wave_shl:1.
 __device__ __forceinline__ float from_upper_lane(float v) {
-    return __int_as_float(
-        __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
 }
 __device__ __forceinline__ double from_lower_lane(double v) {
-    int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, false);
-    int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, false);
+    int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x138, 0xf, 0xf, true);
+    int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x138, 0xf, 0xf, true);
     return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ double from_upper_lane(double v) {
-    int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, false);
-    int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, false);
+    int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x130, 0xf, 0xf, true);
+    int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x130, 0xf, 0xf, true);
     return __hiloint2double(hi, lo);
 }
 
@@ -92,6 +88,9 @@ __device__ __forceinline__ void load_row(const T *__restrict__ p, unsigned okmas
         V v = *reinterpret_cast<const V *>(p);
 #pragma unroll
         for (int i = 0; i < VX; ++i) out[i] = v[i];
+    } else if constexpr (!EDGE) {
+#pragma unroll
+        for (int i = 0; i < VX; ++i) out[i] = p[i];
     } else {
 #pragma unroll
         for (int i = 0; i < VX; ++i) out[i] = (okmask >> i & 1u) ? p[i] : T(0);
@@ -241,8 +240,12 @@ __device__ __forceinline__ void jacobi_tile(const JacArgs<T> &A, int tx, int ty,
         for (int tau = 1; tau <= TB; ++tau) {
             const int p = s - tau;  // plane of level tau produced now
             const int ce = top_bnd ? ze - 1 : ze - tau;
+            // Planes outside [zb+1, ce] take the value of the level below:
+            // ghost planes keep their Dirichlet value, elsewhere the value is
+            // never used.
+            const bool inr = FULL || (p >= zb + 1 && p <= ce);
             T Ncur[RY][VX];
-            if (FULL || (p >= zb + 1 && p <= ce)) {
+            auto update = [&]() {
                 // in-plane neighbours of L_{tau-1}[p] = Aa[tau-1]
                 T lft[RY], rgt[RY], ytop[VX], ybot[VX];
 #pragma unroll
@@ -261,7 +264,16 @@ __device__ __forceinline__ void jacobi_tile(const JacArgs<T> &A, int tx, int ty,
                         ytop[v] = Aa[tau - 1][0][v], ybot[v] = Aa[tau - 1][RY - 1][v];
                 }
                 T fv[RY][VX];
-                if constexpr (HAS_F) load_f(p, fv);
+                if constexpr (HAS_F) {
+                    if (inr) {
+                        load_f(p, fv);
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < RY; ++r)
+#pragma unroll
+                            for (int v = 0; v < VX; ++v) fv[r][v] = T(0);
+                    }
+                }
 #pragma unroll
                 for (int r = 0; r < RY; ++r)
 #pragma unroll
@@ -286,9 +298,8 @@ __device__ __forceinline__ void jacobi_tile(const JacArgs<T> &A, int tx, int ty,
                         Ncur[r][v] = val;
                         Bb[tau - 1][r][v] = Nprev[r][v];
                     }
-            } else {
-                // no computation at this plane: every level equals the level
-                // below there (ghost planes), or the value is never used
+            };
+            auto copy_below = [&]() {
 #pragma unroll
                 for (int r = 0; r < RY; ++r)
 #pragma unroll
@@ -296,6 +307,19 @@ __device__ __forceinline__ void jacobi_tile(const JacArgs<T> &A, int tx, int ty,
                         Ncur[r][v] = Aa[tau - 1][r][v];
                         Bb[tau - 1][r][v] = Nprev[r][v];
                     }
+            };
+            if constexpr (TB >= 2) {
+                // The update runs on every step (it reads only registers and
+                // LDS) and the few fill/drain steps overwrite it afterwards: the
+                // common path then carries no register copies.  (Measured: this
+                // is faster for TB >= 2 and slower for TB = 1.)
+                update();
+                if (__builtin_expect(!inr, 0)) copy_below();
+            } else {
+                if (inr)
+                    update();
+                else
+                    copy_below();
             }
 #pragma unroll
             for (int r = 0; r < RY; ++r)
