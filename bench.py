@@ -31,6 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+SECTIONS = ("copy", "by_t", "fp32", "gs", "poisson", "serving")
 
 
 def bytes_per_lup(elem_bytes: int, t: int) -> float:
@@ -76,7 +77,10 @@ def parse():
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--sweeps", type=int, default=100)
     ap.add_argument("--t", type=int, default=0, help="fused sweeps per pass (0 = library choice)")
-    ap.add_argument("--quick", action="store_true", help="headline only")
+    ap.add_argument("--quick", action="store_true", help="headline only (same as --sections none)")
+    ap.add_argument("--sections", default="all",
+                    help="extra measurements after the headline, comma separated: "
+                         "copy,by_t,fp32,gs,poisson,serving (or all / none)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--poisson-n", type=int, default=256)
     ap.add_argument("--serving-jobs", type=int, default=300)
@@ -277,8 +281,15 @@ def main():
         del a, b
 
     extra = {}
-    if not args.quick:
+    sections = set() if args.quick or args.sections == "none" else (
+        set(SECTIONS) if args.sections == "all" else set(args.sections.split(",")))
+    unknown = sections - set(SECTIONS)
+    if unknown:
+        print("unknown sections: %s" % ",".join(sorted(unknown)), file=sys.stderr)
+        sys.exit(2)
+    if "copy" in sections:
         extra["copy_GBs"] = round(copy_bandwidth(torch), 1)
+    if "by_t" in sections:
         per_t = {}
         for t in (1, 2, 4, 8, 16):
             pl, _ = P.jacobi_plan(S, t)
@@ -293,6 +304,7 @@ def main():
         extra["jacobi_fp64_by_t"] = per_t
         extra["speedup_best_vs_t1"] = round(
             max(v["MLUPs"] for v in per_t.values()) / per_t["1"]["MLUPs"], 2)
+    if "fp32" in sections:
         # FP32 storage
         u32 = u.float()
         s32 = torch.empty_like(u32)
@@ -306,6 +318,7 @@ def main():
             log("jacobi fp32 t=%d: %s" % (t, per32[str(t)]))
         extra["jacobi_fp32_by_t"] = per32
         del u32, s32
+    if "gs" in sections:
         # Gauss-Seidel wavefront, 384^3 x 50
         g = si.gs_384(seed=0)
         ug = torch.from_numpy(g["u"]).to("cuda")
@@ -321,15 +334,15 @@ def main():
             log("gs 384^3 x50 %s: %s" % (key, gs[key]))
         extra["gs_384_x50"] = gs
         del ug, u0
-        torch.cuda.synchronize()
-        # free the 512^3 grids before the remaining measurements
-        del u, s
-        torch.cuda.empty_cache()
-        if args.poisson_n > 0:
-            extra["poisson_%d" % args.poisson_n] = poisson_compare(P, torch, args.poisson_n)
-        if args.serving_jobs > 0:
-            extra["serving"] = serving_stream(P, args.serving_jobs, args.serving_rate)
-            log("serving: %s" % extra["serving"])
+    torch.cuda.synchronize()
+    # free the 512^3 grids before the remaining measurements
+    del u, s
+    torch.cuda.empty_cache()
+    if "poisson" in sections and args.poisson_n > 0:
+        extra["poisson_%d" % args.poisson_n] = poisson_compare(P, torch, args.poisson_n)
+    if "serving" in sections and args.serving_jobs > 0:
+        extra["serving"] = serving_stream(P, args.serving_jobs, args.serving_rate)
+        log("serving: %s" % extra["serving"])
 
     line = {
         "metric": "MLUP/s & HBM-roofline fraction at 512^3 (FP64 vs FP32-refined); job p50/p99",
