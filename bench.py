@@ -119,17 +119,19 @@ def jacobi_run(P, torch, u, s, sweeps, t):
     P.jacobi(u, s, sweeps, a=0.0, b=1.0 / 6.0, t_fuse=t)
 
 
-def cpu_baseline(n, target_s=12.0):
+def cpu_baseline(n, target_s=15.0):
     """The CPU oracle (single thread, as it stands) on a bounded sample."""
     import oracle
     import synthetic_inputs as si
     lib = oracle.load()
     u = si.jacobi_512(seed=0, n=n)["u"]
-    # calibrate on 1 sweep, then run enough sweeps for ~target_s seconds
+    # one untimed sweep (first-touch of the buffers), one timed sweep to
+    # calibrate, then enough sweeps for ~target_s seconds
+    oracle.jacobi(u, 1, lib=lib)
     t0 = time.perf_counter()
     oracle.jacobi(u, 1, lib=lib)
     one = time.perf_counter() - t0
-    S = max(1, min(100, int(target_s / max(one, 1e-3))))
+    S = max(1, min(100, int(round(target_s / max(one, 1e-3)))))
     t0 = time.perf_counter()
     oracle.jacobi(u, S, lib=lib)
     dt = time.perf_counter() - t0
