@@ -546,7 +546,13 @@ hipError_t launch_gs_batch_t(const std::vector<GsBatchItem> &items, GsBatchWork 
         }
     const size_t jobs_bytes = nj_ * sizeof(GsJob<T>);
     const size_t items_bytes = w.items.size() * sizeof(uint64_t);
-    const size_t need = jobs_bytes + items_bytes + ncount * sizeof(uint32_t) + 256 + 512;
+    // one device buffer: jobs | items | progress counters | ticket, each part
+    // starting on a 256-byte boundary
+    auto up256 = [](size_t n) { return (n + 255) / 256 * 256; };
+    const size_t off_items = up256(jobs_bytes);
+    const size_t off_prog = off_items + up256(items_bytes);
+    const size_t off_ticket = off_prog + up256(ncount * sizeof(uint32_t));
+    const size_t need = off_ticket + 256;
     if (w.dev_bytes < need) {
         if (w.dev) (void)hipFree(w.dev);
         w.dev = nullptr;
@@ -557,10 +563,9 @@ hipError_t launch_gs_batch_t(const std::vector<GsBatchItem> &items, GsBatchWork 
     }
     char *base = static_cast<char *>(w.dev);
     GsJob<T> *djobs = reinterpret_cast<GsJob<T> *>(base);
-    uint64_t *ditems = reinterpret_cast<uint64_t *>(base + ((jobs_bytes + 255) / 256) * 256);
-    uint32_t *dprog = reinterpret_cast<uint32_t *>(
-        reinterpret_cast<char *>(ditems) + ((items_bytes + 255) / 256) * 256);
-    uint32_t *dticket = dprog + ((ncount + 63) / 64) * 64;
+    uint64_t *ditems = reinterpret_cast<uint64_t *>(base + off_items);
+    uint32_t *dprog = reinterpret_cast<uint32_t *>(base + off_prog);
+    uint32_t *dticket = reinterpret_cast<uint32_t *>(base + off_ticket);
     w.jobs_host.resize(jobs_bytes);
     GsJob<T> *hj = reinterpret_cast<GsJob<T> *>(w.jobs_host.data());
     for (size_t j = 0; j < nj_; ++j)

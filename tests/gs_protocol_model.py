@@ -35,7 +35,13 @@ def staged_slot(li):
     if li < 88: return 10 + (li - 8)
     return 90 + (li - 88) + 1
 
-def simulate(u0, S, h=1, workers=3, seed=0, a=0.0, b=1/6):
+def simulate(u0, S, h=1, workers=3, seed=0, a=0.0, b=1/6, p_early=0.3, publish_lag=3):
+    """Run the schedule with `workers` interleaved waves.  Every global load
+    and store takes effect at a random moment between its issue and the next
+    point where the kernel waits for all of its memory operations (a chunk
+    load may also be needed earlier, at its commit to LDS).  publish_lag is
+    the kernel's 3 (boundary b publishes chunk b-3, whose stores were issued
+    one boundary earlier); 2 would publish a chunk before its stores."""
     u = u0.copy()
     pz, py, px = u.shape
     nz, ny, nx = pz-2*h, py-2*h, px-2*h
@@ -50,7 +56,8 @@ def simulate(u0, S, h=1, workers=3, seed=0, a=0.0, b=1/6):
             if d in pos: assert pos[d] < n, ("not topological", d, (tau, J, K))
     P = np.zeros((S, nj*nk), dtype=np.int64)
     ticket = [0]
-    
+    rng = random.Random(seed)
+
     def worker():
         while True:
             t = ticket[0]; ticket[0] += 1
@@ -64,6 +71,14 @@ def simulate(u0, S, h=1, workers=3, seed=0, a=0.0, b=1/6):
             for l, (jj, kk) in enumerate(lanes):
                 j, k = j0+jj, k0+kk
                 if j < h+ny and k < h+nz: xm[l] = u[k, j, h-1]
+            pending = []   # memory operations issued and not yet performed
+            def tick():    # some of them take effect now
+                for op in list(pending):
+                    if rng.random() < p_early:
+                        pending.remove(op); op()
+            def wait_all():  # the kernel waits for every memory operation
+                while pending:
+                    pending.pop(0)()
             def wait_chunk(c):
                 if c*C >= nx: return
                 conds = []
@@ -77,24 +92,34 @@ def simulate(u0, S, h=1, workers=3, seed=0, a=0.0, b=1/6):
                     while P[q0, q1] < c + 1:
                         yield "wait"
             pf = {}
-            def issue_load(c):  # global -> registers (values read now)
-                vals = []
-                for e in range(768):
-                    li = e >> 3; i = c*C + (e & 7)
-                    slot = staged_slot(li); jl, kl = slot % 10, slot // 10
-                    jg, kg = j0-1+jl, k0-1+kl
-                    ok = i <= nx and jg <= h+ny and kg <= h+nz
-                    vals.append((slot, i & (RING-1), u[kg, jg, h+i] if ok else 0.0))
-                pf["c"] = vals
-            def commit_load(c):  # registers -> LDS ring
-                for slot, r, v in pf["c"]:
+            def issue_load(c):  # global -> registers, read at some later moment
+                vals = {}
+                def read():
+                    for e in range(768):
+                        li = e >> 3; i = c*C + (e & 7)
+                        slot = staged_slot(li); jl, kl = slot % 10, slot // 10
+                        jg, kg = j0-1+jl, k0-1+kl
+                        ok = i <= nx and jg <= h+ny and kg <= h+nz
+                        vals[e] = (slot, i & (RING-1), u[kg, jg, h+i] if ok else 0.0)
+                pf["c"] = (vals, read)
+                pending.append(read)
+            def commit_load(c):  # registers -> LDS ring (the load has completed)
+                vals, read = pf["c"]
+                if read in pending:
+                    pending.remove(read); read()
+                for slot, r, v in vals.values():
                     ring[slot, r] = v
-            def issue_store(c):  # LDS -> global, not yet published
+            def issue_store(c):  # LDS read now; global write at some later moment
+                vals = []
                 for e in range(512):
                     li = e >> 3; i = c*C + (e & 7); jq, kq = li & 7, li >> 3
                     jg, kg = j0+jq, k0+kq
                     if i < nx and jg < h+ny and kg < h+nz:
-                        u[kg, jg, h+i] = ring[(kq+1)*10 + jq+1, i & (RING-1)]
+                        vals.append((kg, jg, h+i, ring[(kq+1)*10 + jq+1, i & (RING-1)]))
+                def write():
+                    for kg, jg, ig, v in vals:
+                        u[kg, jg, ig] = v
+                pending.append(write)
             def publish(c):
                 P[tau, me] = c + 1
             yield from wait_chunk(0); issue_load(0); commit_load(0)
@@ -118,17 +143,20 @@ def simulate(u0, S, h=1, workers=3, seed=0, a=0.0, b=1/6):
                             writes.append((own, p, v, l))
                     for own, p, v, l in writes:
                         ring[own, p] = v; xm[l] = v
+                    tick()
                     yield "step"
-                if 0 <= bb-3 < ncs: publish(bb-3)
+                wait_all()
+                if 0 <= bb-publish_lag < ncs: publish(bb-publish_lag)
                 yield "boundary"
                 if 0 <= bb-2 < ncs: issue_store(bb-2)
+                tick()
                 if bb+2 < ncl: commit_load(bb+2)
                 if bb+3 < ncl:
                     yield from wait_chunk(bb+3); issue_load(bb+3)
+            wait_all()
             if 0 <= nb-3 < ncs: publish(nb-3)
             for cs in range(max(0, nb-2), ncs):
-                issue_store(cs); publish(cs)
-    rng = random.Random(seed)
+                issue_store(cs); wait_all(); publish(cs)
     ws = [worker() for _ in range(workers)]
     stall = 0
     while ws:
@@ -140,4 +168,3 @@ def simulate(u0, S, h=1, workers=3, seed=0, a=0.0, b=1/6):
         except StopIteration:
             ws.remove(w)
     return u
-
