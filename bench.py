@@ -83,8 +83,11 @@ def parse():
                          "copy,by_t,fp32,gs,poisson,serving (or all / none)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--poisson-n", type=int, default=256)
+    ap.add_argument("--poisson-m", type=int, default=32, help="inner sweeps per outer round")
+    ap.add_argument("--poisson-methods", default="jacobi,gs")
     ap.add_argument("--serving-jobs", type=int, default=300)
-    ap.add_argument("--serving-rate", type=float, default=200.0)
+    ap.add_argument("--serving-rate", default="200",
+                    help="arrival rate(s) per second, comma separated")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 2 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -141,9 +144,13 @@ def cpu_baseline(n, target_s=15.0):
                       "C oracle, %.1f s" % (n, S, dt)}
 
 
-def poisson_compare(P, torch, n, seed=0, methods=(0, 1), m=32, tol=1e-10):
+def poisson_compare(P, torch, n, seed=0, methods=(0, 1), m=32, tol=1e-10, chunk_s=30.0):
     """-Laplace u = f on n^3, h = 1/(n+1), f U[-1,1), u0 = 0: time to reach
-    ||f' - A u|| <= tol ||f'|| with the FP32-refined loop and the plain FP64 method."""
+    ||f' - A u|| <= tol ||f'|| with the FP32-refined loop and the plain FP64
+    method.  The solve runs as consecutive library calls of a bounded number
+    of outer rounds (each call continues from the current u and re-checks the
+    residual first, so the iterates are those of one uninterrupted solve),
+    with a progress line after each call."""
     import synthetic_inputs as si
     w = si.poisson(n=n, seed=seed)
     fp = torch.from_numpy(w["f"] / float((n + 1) ** 2)).to("cuda")
@@ -155,9 +162,21 @@ def poisson_compare(P, torch, n, seed=0, methods=(0, 1), m=32, tol=1e-10):
             u = torch.from_numpy(w["u"]).to("cuda")
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            rounds, rel, rc = P.refine_solve(u, fp, method=method, inner_fp32=inner_fp32,
-                                             inner_sweeps=m, rel_tol=tol, max_outer=10 ** 7,
-                                             raise_on_noconv=False)
+            rounds, rel, rc, per_call = 0, 1.0, -6, 16
+            while True:
+                t1 = time.perf_counter()
+                r, rel, rc = P.refine_solve(u, fp, method=method, inner_fp32=inner_fp32,
+                                            inner_sweeps=m, rel_tol=tol, max_outer=per_call,
+                                            raise_on_noconv=False)
+                torch.cuda.synchronize()
+                rounds += r
+                dt_call = time.perf_counter() - t1
+                log("poisson %d^3 %s %s: %d rounds, rel %.3e, %.1f s" %
+                    (n, name, key, rounds, rel, time.perf_counter() - t0))
+                if rc == 0 or rounds >= 10 ** 7:
+                    break
+                # size the next call for about chunk_s seconds
+                per_call = max(1, min(10 ** 6, int(per_call * chunk_s / max(dt_call, 1e-3))))
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             sweeps = rounds * m
@@ -341,10 +360,17 @@ def main():
     del u, s
     torch.cuda.empty_cache()
     if "poisson" in sections and args.poisson_n > 0:
-        extra["poisson_%d" % args.poisson_n] = poisson_compare(P, torch, args.poisson_n)
+        names = {"jacobi": 0, "gs": 1}
+        methods = tuple(names[x] for x in args.poisson_methods.split(","))
+        extra["poisson_%d" % args.poisson_n] = poisson_compare(P, torch, args.poisson_n,
+                                                               methods=methods, m=args.poisson_m)
     if "serving" in sections and args.serving_jobs > 0:
-        extra["serving"] = serving_stream(P, args.serving_jobs, args.serving_rate)
-        log("serving: %s" % extra["serving"])
+        rates = [float(x) for x in str(args.serving_rate).split(",")]
+        runs = []
+        for rate in rates:
+            runs.append(serving_stream(P, args.serving_jobs, rate))
+            log("serving: %s" % runs[-1])
+        extra["serving"] = runs[0] if len(runs) == 1 else runs
 
     line = {
         "metric": "MLUP/s & HBM-roofline fraction at 512^3 (FP64 vs FP32-refined); job p50/p99",

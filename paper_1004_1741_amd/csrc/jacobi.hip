@@ -115,9 +115,26 @@ __device__ __forceinline__ void store_row(T *__restrict__ p, unsigned mask, cons
         if (mask >> i & 1u) p[i] = v[i];
 }
 
+// Right-hand side ring: each thread keeps the f values of its own sites for
+// planes s-2 .. s-TB (needed by levels 2..TB at step s) in LDS, so f is read
+// from memory once per pass instead of once per level.  Used where it fits
+// next to the exchange buffer in the 160 KB of LDS.
+template <typename T, int TB, int VX, int RY, int NW, bool HAS_F>
+struct FRing {
+    static constexpr size_t xch_bytes = (size_t)2 * TB * NW * 2 * 64 * VX * sizeof(T);
+    static constexpr size_t ring_elems = (size_t)(TB > 1 ? TB - 1 : 0) * RY * VX * NW * 64;
+    static constexpr bool on =
+        HAS_F && TB >= 2 && xch_bytes + ring_elems * sizeof(T) <= 160 * 1024;
+    static constexpr size_t alloc = on ? ring_elems : 1;
+};
+
 template <typename T, int TB, int VX, int RY, int NW, bool HAS_A, bool HAS_F, bool EDGE>
 __device__ __forceinline__ void jacobi_tile(const JacArgs<T> &A, int tx, int ty, int cz,
-                                            T (*xch)[TB][NW][2][64 * VX]) {
+                                            T (*xch)[TB][NW][2][64 * VX], T *fring) {
+    constexpr bool RING = FRing<T, TB, VX, RY, NW, HAS_F>::on;
+    // level 1 takes f from registers loaded one step early when the ring is
+    // used; otherwise every level loads its own f plane
+    constexpr bool FPRE = RING;
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const int h = A.h;
@@ -176,8 +193,11 @@ __device__ __forceinline__ void jacobi_tile(const JacArgs<T> &A, int tx, int ty,
         }
     };
     auto load_f = [&](int z, T (&out)[RY][VX]) {
-        // f is interior-only: f[((z-h)*ny + (y-h))*nx + (x-h)]
-        const T *base = A.f + ((int64_t)(z - h) * A.ny) * A.nx;
+        // f is interior-only: f[((z-h)*ny + (y-h))*nx + (x-h)].  Planes
+        // outside the interior (only read by levels that copy there) are
+        // clamped to a valid plane.
+        const int zc = min(max(z, h), h + A.nz - 1);
+        const T *base = A.f + ((int64_t)(zc - h) * A.ny) * A.nx;
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
             const unsigned ok = (updy >> r & 1u) ? updx : 0u;
@@ -198,6 +218,18 @@ __device__ __forceinline__ void jacobi_tile(const JacArgs<T> &A, int tx, int ty,
     T P0[TB][RY][VX];
     T P1[TB][RY][VX];
     T nxt[RY][VX];
+    // f of plane s-1 (for level 1 at step s) and of plane s (loaded at step s),
+    // alternating like P0/P1
+    T F0[FPRE ? RY : 1][VX];
+    T F1[FPRE ? RY : 1][VX];
+    const int tid = threadIdx.x;
+    auto ring_slot = [&](int plane) {
+        constexpr int M = TB > 1 ? TB - 1 : 1;
+        return ((plane % M) + M) % M;
+    };
+    auto ring_at = [&](int slot, int r, int v) -> T & {
+        return fring[((slot * RY + r) * VX + v) * (NW * 64) + tid];
+    };
 
     auto exchange = [&](int buf, T (&Anew)[TB][RY][VX]) {
         if constexpr (NW > 1) {
@@ -222,12 +254,14 @@ __device__ __forceinline__ void jacobi_tile(const JacArgs<T> &A, int tx, int ty,
 #pragma unroll
             for (int v = 0; v < VX; ++v) P0[k][r][v] = nxt[r][v], P1[k][r][v] = nxt[r][v];
     if (zb + 1 <= ze) load_plane(zb + 1, nxt);
+    if constexpr (FPRE) load_f(zb, F0);
     int buf = 0;
     exchange(buf, P0);
     const int s_end = z1 - 1 + TB;
 
     // FULL: steady state, every level produces and the next plane exists
-    auto step = [&](int s, T (&Aa)[TB][RY][VX], T (&Bb)[TB][RY][VX], auto full_c) {
+    auto step = [&](int s, T (&Aa)[TB][RY][VX], T (&Bb)[TB][RY][VX],
+                    T (&Fc)[FPRE ? RY : 1][VX], T (&Fn)[FPRE ? RY : 1][VX], auto full_c) {
         constexpr bool FULL = decltype(full_c)::value;
         T Nprev[RY][VX];  // new plane of level tau-1 (level 0: plane s, loaded)
 #pragma unroll
@@ -235,6 +269,7 @@ __device__ __forceinline__ void jacobi_tile(const JacArgs<T> &A, int tx, int ty,
 #pragma unroll
             for (int v = 0; v < VX; ++v) Nprev[r][v] = nxt[r][v];
         if (FULL || s + 1 <= ze) load_plane(s + 1, nxt);
+        if constexpr (FPRE) load_f(s, Fn);  // for level 1 at step s+1
 
 #pragma unroll
         for (int tau = 1; tau <= TB; ++tau) {
@@ -263,9 +298,20 @@ __device__ __forceinline__ void jacobi_tile(const JacArgs<T> &A, int tx, int ty,
                     for (int v = 0; v < VX; ++v)
                         ytop[v] = Aa[tau - 1][0][v], ybot[v] = Aa[tau - 1][RY - 1][v];
                 }
-                T fv[RY][VX];
+                T fv[HAS_F ? RY : 1][VX];
                 if constexpr (HAS_F) {
-                    if (inr) {
+                    if (FPRE && tau == 1) {
+#pragma unroll
+                        for (int r = 0; r < RY; ++r)
+#pragma unroll
+                            for (int v = 0; v < VX; ++v) fv[r][v] = Fc[FPRE ? r : 0][v];
+                    } else if constexpr (RING) {
+                        const int sl = ring_slot(p);
+#pragma unroll
+                        for (int r = 0; r < RY; ++r)
+#pragma unroll
+                            for (int v = 0; v < VX; ++v) fv[r][v] = ring_at(sl, r, v);
+                    } else if (inr) {
                         load_f(p, fv);
                     } else {
 #pragma unroll
@@ -326,6 +372,15 @@ __device__ __forceinline__ void jacobi_tile(const JacArgs<T> &A, int tx, int ty,
 #pragma unroll
                 for (int v = 0; v < VX; ++v) Nprev[r][v] = Ncur[r][v];
         }
+        // plane s-1 of f joins the ring, in the slot of plane s-TB (read by
+        // level TB above: each thread only touches its own entries, in order)
+        if constexpr (RING) {
+            const int sl = ring_slot(s - 1);
+#pragma unroll
+            for (int r = 0; r < RY; ++r)
+#pragma unroll
+                for (int v = 0; v < VX; ++v) ring_at(sl, r, v) = Fc[r][v];
+        }
         // store level TB of plane s-TB
         const int p = s - TB;
         if (p >= z0 && p < z1) {
@@ -341,15 +396,16 @@ __device__ __forceinline__ void jacobi_tile(const JacArgs<T> &A, int tx, int ty,
     using Part = std::integral_constant<bool, false>;
     int s = zb + 1;
     for (; s + 1 <= s_end; s += 2) {
-        step(s, P0, P1, Part{});
-        step(s + 1, P1, P0, Part{});
+        step(s, P0, P1, F0, F1, Part{});
+        step(s + 1, P1, P0, F1, F0, Part{});
     }
-    if (s <= s_end) step(s, P0, P1, Part{});
+    if (s <= s_end) step(s, P0, P1, F0, F1, Part{});
 }
 
 template <typename T, int TB, int VX, int RY, int NW, bool HAS_A, bool HAS_F>
 __global__ void __launch_bounds__(NW * 64) jacobi_pass_kernel(JacArgs<T> A) {
     __shared__ T xch[2][TB][NW][2][64 * VX];
+    __shared__ T fring[FRing<T, TB, VX, RY, NW, HAS_F>::alloc];
     // The dispatcher places consecutive workgroup ids round-robin on the 8
     // XCDs; give each XCD a contiguous range of tiles so that neighbouring
     // tiles (which re-read each other's overlap) share an L2.
@@ -372,9 +428,9 @@ __global__ void __launch_bounds__(NW * 64) jacobi_pass_kernel(JacArgs<T> A) {
     const bool interior = xs >= A.h && xs + 64 * VX <= A.h + A.nx && ys >= A.h &&
                           ys + NW * RY <= A.h + A.ny;
     if (interior)
-        jacobi_tile<T, TB, VX, RY, NW, HAS_A, HAS_F, false>(A, tx, ty, cz, xch);
+        jacobi_tile<T, TB, VX, RY, NW, HAS_A, HAS_F, false>(A, tx, ty, cz, xch, fring);
     else
-        jacobi_tile<T, TB, VX, RY, NW, HAS_A, HAS_F, true>(A, tx, ty, cz, xch);
+        jacobi_tile<T, TB, VX, RY, NW, HAS_A, HAS_F, true>(A, tx, ty, cz, xch, fring);
 }
 
 // Batched pass: one launch advances several independent grids (jobs of the
@@ -393,6 +449,7 @@ template <typename T, int TB, int VX, int RY, int NW, bool HAS_A, bool HAS_F>
 __global__ void __launch_bounds__(NW * 64)
     jacobi_batch_kernel(const JacJob<T> *__restrict__ jobs, int njobs, int total) {
     __shared__ T xch[2][TB][NW][2][64 * VX];
+    __shared__ T fring[FRing<T, TB, VX, RY, NW, HAS_F>::alloc];
     const int G = gridDim.x;
     const int per = G >> 3;
     const int bid = blockIdx.x;
@@ -417,9 +474,9 @@ __global__ void __launch_bounds__(NW * 64)
     const bool interior = xs >= A.h && xs + 64 * VX <= A.h + A.nx && ys >= A.h &&
                           ys + NW * RY <= A.h + A.ny;
     if (interior)
-        jacobi_tile<T, TB, VX, RY, NW, HAS_A, HAS_F, false>(A, tx, ty, cz, xch);
+        jacobi_tile<T, TB, VX, RY, NW, HAS_A, HAS_F, false>(A, tx, ty, cz, xch, fring);
     else
-        jacobi_tile<T, TB, VX, RY, NW, HAS_A, HAS_F, true>(A, tx, ty, cz, xch);
+        jacobi_tile<T, TB, VX, RY, NW, HAS_A, HAS_F, true>(A, tx, ty, cz, xch, fring);
 }
 
 // Tile configurations (VX, RY, NW), chosen by measurement on MI355X among
@@ -436,12 +493,15 @@ template <> struct CfgBase<float, 1> { static constexpr int VX = 2, RY = 8, NW =
 template <> struct CfgBase<float, 2> { static constexpr int VX = 2, RY = 8, NW = 8; };
 template <> struct CfgBase<float, 4> { static constexpr int VX = 2, RY = 6, NW = 8; };
 template <> struct CfgBase<float, 8> { static constexpr int VX = 1, RY = 8, NW = 8; };
-// With a right-hand side the f values of each level add register pressure:
-// the deepest FP64 shapes would spill, so they use shallower tiles.
+// With a right-hand side the prefetched f planes add register pressure and
+// the f ring needs LDS next to the exchange buffer: some shapes are shorter
+// (FP32 t=8 also so that its ring fits; FP64 t=8 has no room for the ring
+// and loads f per level).
 template <typename T, int TB, bool HAS_F>
 struct Cfg : CfgBase<T, TB> {};
 template <> struct Cfg<double, 4, true> { static constexpr int VX = 1, RY = 6, NW = 8; };
 template <> struct Cfg<double, 8, true> { static constexpr int VX = 1, RY = 4, NW = 8; };
+template <> struct Cfg<float, 8, true> { static constexpr int VX = 1, RY = 6, NW = 8; };
 
 template <typename T, int TB, bool HAS_F = false>
 JacTileCfg cfg_of() {

@@ -10,8 +10,10 @@
 //     Jobs admitted while an iteration runs join the next one, so their work
 //     overlaps with the others' on the device (iteration-level continuous
 //     batching);
-//   * uploader / downloader: host<->device copies of job grids on their own
-//     streams, so copies overlap with the iterations.
+//   * uploaders / downloaders (kIoThreads of each): host<->device copies of
+//     job grids on their own streams, so copies overlap with the iterations
+//     and with each other (a single copy thread is limited by the runtime's
+//     staging of pageable host memory).
 // Batched kernels run each job's tiles/items exactly as the single-grid
 // kernels do, so a job's result does not depend on its batch companions.
 #include <hip/hip_runtime.h>
@@ -82,11 +84,15 @@ uint64_t footprint(const smooth_job &j) {
 
 using namespace stk;
 
+// host<->device copy threads per direction
+constexpr int kIoThreads = 4;
+
 struct smooth_ctx {
     smooth_config cfg{};
     void *pool = nullptr;
     PoolAllocator alloc;
-    hipStream_t s_comp = nullptr, s_up = nullptr, s_down = nullptr;
+    hipStream_t s_comp = nullptr;
+    std::vector<hipStream_t> s_up, s_down;  // one per copy thread
     hipEvent_t ev_iter = nullptr;
     std::mutex mu;
     std::condition_variable cv;       // scheduler wake-ups
@@ -99,7 +105,8 @@ struct smooth_ctx {
     std::map<uint64_t, std::unique_ptr<Job>> jobs;
     uint64_t next_id = 1;
     bool stop = false, sched_done = false;
-    std::thread th_sched, th_up, th_down;
+    std::thread th_sched;
+    std::vector<std::thread> th_up, th_down;
     int64_t batches = 0, n_done = 0, n_failed = 0, n_canceled = 0;
     int max_resident = 0;
     int gs_chunk = 4;  // Gauss-Seidel sweeps per iteration
@@ -169,7 +176,7 @@ void admit(smooth_ctx *c) {
     }
 }
 
-void uploader(smooth_ctx *c) {
+void uploader(smooth_ctx *c, int k) {
     (void)hipSetDevice(c->cfg.device);
     std::unique_lock<std::mutex> lk(c->mu);
     for (;;) {
@@ -180,8 +187,8 @@ void uploader(smooth_ctx *c) {
         const size_t bytes = (size_t)j->g.count() * sizeof(double);
         lk.unlock();
         hipError_t e =
-            hipMemcpyAsync(j->u, j->spec.input_host, bytes, hipMemcpyHostToDevice, c->s_up);
-        if (e == hipSuccess) e = hipStreamSynchronize(c->s_up);
+            hipMemcpyAsync(j->u, j->spec.input_host, bytes, hipMemcpyHostToDevice, c->s_up[k]);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->s_up[k]);
         lk.lock();
         if (e != hipSuccess) {
             set_error(std::string("job upload: ") + hipGetErrorString(e));
@@ -193,7 +200,7 @@ void uploader(smooth_ctx *c) {
     }
 }
 
-void downloader(smooth_ctx *c) {
+void downloader(smooth_ctx *c, int k) {
     (void)hipSetDevice(c->cfg.device);
     std::unique_lock<std::mutex> lk(c->mu);
     for (;;) {
@@ -206,8 +213,8 @@ void downloader(smooth_ctx *c) {
         hipError_t e = hipEventSynchronize(j->ev_done);
         if (e == hipSuccess)
             e = hipMemcpyAsync(j->spec.output_host, j->result, bytes, hipMemcpyDeviceToHost,
-                               c->s_down);
-        if (e == hipSuccess) e = hipStreamSynchronize(c->s_down);
+                               c->s_down[k]);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->s_down[k]);
         lk.lock();
         if (e != hipSuccess) set_error(std::string("job download: ") + hipGetErrorString(e));
         finish(c, j, e == hipSuccess ? SMOOTH_DONE : SMOOTH_FAILED);
@@ -439,17 +446,29 @@ int smooth_init(const smooth_config *cfg, smooth_ctx **out) {
         return fail(ST_ENOMEM, std::string("job pool: ") + hipGetErrorString(e));
     }
     c->alloc.reset(cfg->hbm_budget_bytes);
-    if ((e = hipStreamCreateWithFlags(&c->s_comp, hipStreamNonBlocking)) != hipSuccess ||
-        (e = hipStreamCreateWithFlags(&c->s_up, hipStreamNonBlocking)) != hipSuccess ||
-        (e = hipStreamCreateWithFlags(&c->s_down, hipStreamNonBlocking)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&c->ev_iter, hipEventDisableTiming)) != hipSuccess) {
+    c->s_up.assign(kIoThreads, nullptr);
+    c->s_down.assign(kIoThreads, nullptr);
+    e = hipStreamCreateWithFlags(&c->s_comp, hipStreamNonBlocking);
+    for (int k = 0; k < kIoThreads && e == hipSuccess; ++k) {
+        e = hipStreamCreateWithFlags(&c->s_up[k], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->s_down[k], hipStreamNonBlocking);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_iter, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        for (hipStream_t st : c->s_up)
+            if (st) (void)hipStreamDestroy(st);
+        for (hipStream_t st : c->s_down)
+            if (st) (void)hipStreamDestroy(st);
+        if (c->s_comp) (void)hipStreamDestroy(c->s_comp);
         (void)hipFree(c->pool);
         return fail(ST_EHIP, std::string("job service streams: ") + hipGetErrorString(e));
     }
     smooth_ctx *p = c.release();
     p->th_sched = std::thread(scheduler, p);
-    p->th_up = std::thread(uploader, p);
-    p->th_down = std::thread(downloader, p);
+    for (int k = 0; k < kIoThreads; ++k) {
+        p->th_up.emplace_back(uploader, p, k);
+        p->th_down.emplace_back(downloader, p, k);
+    }
     *out = p;
     return ST_OK;
 }
@@ -555,8 +574,10 @@ int smooth_shutdown(smooth_ctx *c) {
         c->cv_io.notify_all();
     }
     if (c->th_sched.joinable()) c->th_sched.join();
-    if (c->th_up.joinable()) c->th_up.join();
-    if (c->th_down.joinable()) c->th_down.join();
+    for (auto &t : c->th_up)
+        if (t.joinable()) t.join();
+    for (auto &t : c->th_down)
+        if (t.joinable()) t.join();
     (void)hipSetDevice(c->cfg.device);
     (void)hipDeviceSynchronize();
     for (auto &kv : c->jac_tables)
@@ -564,8 +585,10 @@ int smooth_shutdown(smooth_ctx *c) {
     c->gs_works.clear();
     if (c->ev_iter) (void)hipEventDestroy(c->ev_iter);
     if (c->s_comp) (void)hipStreamDestroy(c->s_comp);
-    if (c->s_up) (void)hipStreamDestroy(c->s_up);
-    if (c->s_down) (void)hipStreamDestroy(c->s_down);
+    for (hipStream_t st : c->s_up)
+        if (st) (void)hipStreamDestroy(st);
+    for (hipStream_t st : c->s_down)
+        if (st) (void)hipStreamDestroy(st);
     if (c->pool) (void)hipFree(c->pool);
     delete c;
     return ST_OK;

@@ -74,7 +74,8 @@ def test_jacobi_ragged(P, olib, case, dtype):
     u = si.uniform_padded(nx, ny, nz, h, seed=nx + 7 * ny, lo=-1.0, hi=1.0).astype(dt)
     f = si.uniform_rhs(nx, ny, nz, seed=3).astype(dt)
     for t in (1, 2, 4, 8):
-        for (a, b, g, ff) in ((0.0, 1.0 / 6.0, 0.0, None), (0.3, 0.1, 0.25, f)):
+        for (a, b, g, ff) in ((0.0, 1.0 / 6.0, 0.0, None), (0.3, 0.1, 0.25, f),
+                              (0.0, 1.0 / 6.0, 1.0 / 6.0, f)):
             say("jacobi", case, dtype, "t=%d a=%g rhs=%s" % (t, a, ff is not None))
             ref = oracle.jacobi(u, S, a=a, b=b, f=ff, g=g, h=h, lib=olib)
             got = _run_jacobi(P, u, S, t, a=a, b=b, f=ff, g=g, h=h)
