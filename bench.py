@@ -31,7 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-SECTIONS = ("copy", "by_t", "fp32", "gs", "poisson", "serving")
+SECTIONS = ("copy", "small", "by_t", "fp32", "gs", "poisson", "serving")
 
 
 def bytes_per_lup(elem_bytes: int, t: int) -> float:
@@ -80,7 +80,7 @@ def parse():
     ap.add_argument("--quick", action="store_true", help="headline only (same as --sections none)")
     ap.add_argument("--sections", default="all",
                     help="extra measurements after the headline, comma separated: "
-                         "copy,by_t,fp32,gs,poisson,serving (or all / none)")
+                         "copy,small,by_t,fp32,gs,poisson,serving (or all / none)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--poisson-n", type=int, default=256)
     ap.add_argument("--poisson-m", type=int, default=32, help="inner sweeps per outer round")
@@ -128,13 +128,17 @@ def cpu_baseline(n, target_s=15.0):
     import synthetic_inputs as si
     lib = oracle.load()
     u = si.jacobi_512(seed=0, n=n)["u"]
-    # one untimed sweep (first-touch of the buffers), one timed sweep to
-    # calibrate, then enough sweeps for ~target_s seconds
+    # one untimed sweep (first-touch of the buffers); the per-sweep cost is
+    # the difference of a 3-sweep and a 1-sweep call (each call also copies
+    # and allocates), then enough sweeps for ~target_s seconds
     oracle.jacobi(u, 1, lib=lib)
     t0 = time.perf_counter()
     oracle.jacobi(u, 1, lib=lib)
-    one = time.perf_counter() - t0
-    S = max(1, min(100, int(round(target_s / max(one, 1e-3)))))
+    t1 = time.perf_counter()
+    oracle.jacobi(u, 3, lib=lib)
+    t3 = time.perf_counter()
+    one = max((t3 - t1) - (t1 - t0), 1e-3) / 2
+    S = max(1, min(100, int(round(target_s / one))))
     t0 = time.perf_counter()
     oracle.jacobi(u, S, lib=lib)
     dt = time.perf_counter() - t0
@@ -142,6 +146,44 @@ def cpu_baseline(n, target_s=15.0):
     return {"value": lups / dt / 1e6, "unit": "MLUP/s", "cores": 1, "kind": "oracle",
             "sample": "FP64 Jacobi %d^3 x %d sweeps (of the 100-sweep step), single-threaded "
                       "C oracle, %.1f s" % (n, S, dt)}
+
+
+def cpu_gs_oracle(n=384, sweeps=50):
+    """The CPU oracle's lexicographic Gauss-Seidel (inherently sequential,
+    single thread) on the full 384^3 x 50 workload."""
+    import oracle
+    import synthetic_inputs as si
+    lib = oracle.load()
+    g = si.gs_384(seed=0, n=n)
+    oracle.gauss_seidel(g["u"], 1, lib=lib)  # first touch
+    t0 = time.perf_counter()
+    oracle.gauss_seidel(g["u"], sweeps, lib=lib)
+    dt = time.perf_counter() - t0
+    return {"value": round(float(n) ** 3 * sweeps / dt / 1e6, 1), "unit": "MLUP/s", "cores": 1,
+            "kind": "oracle", "seconds": round(dt, 3),
+            "sample": "FP64 Gauss-Seidel %d^3 x %d sweeps, single-threaded C oracle" % (n, sweeps)}
+
+
+def small_grids(P, torch):
+    """The 64^3 x 10 smoke configuration: grids of 2.3 MB stay in L2/MALL, so
+    these rates are cache-resident and launch/latency-bound, not HBM numbers."""
+    import synthetic_inputs as si
+    w = si.jacobi_small(seed=0)
+    u = torch.from_numpy(w["u"]).to("cuda")
+    s = torch.empty_like(u)
+    S = w["sweeps"]
+    lups = 64.0 ** 3 * S
+    out = {"label": "cache-resident"}
+    P.jacobi(u, s, S, a=w["a"], b=w["b"])
+    ms = events_time(torch, lambda: P.jacobi(u, s, S, a=w["a"], b=w["b"]), reps=20) / 20
+    out["jacobi_fp64_64cubed_x10"] = {"ms": round(ms, 4), "MLUPs": round(lups / (ms * 1e-3) / 1e6)}
+    g = si.gs_384(seed=0, n=64)
+    ug = torch.from_numpy(g["u"]).to("cuda")
+    P.gauss_seidel(ug, S)
+    ms = events_time(torch, lambda: P.gauss_seidel(ug, S), reps=20) / 20
+    out["gs_fp64_64cubed_x10"] = {"ms": round(ms, 4), "MLUPs": round(lups / (ms * 1e-3) / 1e6)}
+    log("small grids: %s" % out)
+    return out
 
 
 def poisson_compare(P, torch, n, seed=0, methods=(0, 1), m=32, tol=1e-10, chunk_s=30.0):
@@ -310,6 +352,8 @@ def main():
         sys.exit(2)
     if "copy" in sections:
         extra["copy_GBs"] = round(copy_bandwidth(torch), 1)
+    if "small" in sections:
+        extra["small_64cubed"] = small_grids(P, torch)
     if "by_t" in sections:
         per_t = {}
         for t in (1, 2, 4, 8, 16):
@@ -394,6 +438,9 @@ def main():
         line["cpu_baseline"] = cpu_baseline(n)
         line["cpu_baseline"]["host"] = platform.processor() or platform.machine()
         line["cpu_baseline"]["host_threads_available"] = os.cpu_count()
+        if "gs" in sections:
+            extra["cpu_oracle_gs_384_x50"] = cpu_gs_oracle()
+            log("cpu oracle gs: %s" % extra["cpu_oracle_gs_384_x50"])
     line.update(extra)
     print(json.dumps(line), flush=True)
 
