@@ -44,23 +44,30 @@ def eq1_mlups(bandwidth_GBs: float, elem_bytes: int = 8, t: int = 1) -> float:
     return bandwidth_GBs * 1e9 / bytes_per_lup(elem_bytes, t) / 1e6
 
 
+def jacobi_source_sha(t):
+    """Hash of the fused-pass kernel source as built for depth t."""
+    import hashlib
+    cs = os.path.join(ROOT, "paper_1004_1741_amd", "csrc")
+    h = hashlib.sha256()
+    for name in ("jacobi_impl.h", "jacobi_t%d.hip" % t):
+        h.update(open(os.path.join(cs, name), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def measured_traffic(kernel_t, n):
     """HBM bytes per launch of the dominant kernel from the committed
     rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, each scaled by the
     plain-copy calibration), or None if that summary does not describe the
     kernel as it is now built (source changed) or this workload."""
-    import hashlib
-    prof = os.path.join(ROOT, "profiles", "jacobi_pass_fp64_t4_512cubed.md")
-    src = os.path.join(ROOT, "paper_1004_1741_amd", "csrc", "jacobi.hip")
-    if kernel_t != 4 or n != 512 or not os.path.exists(prof):
+    prof = os.path.join(ROOT, "profiles", "jacobi_pass_fp64_t%d_512cubed.md" % kernel_t)
+    if n != 512 or not os.path.exists(prof):
         return None
     vals = {}
     for line in open(prof):
         if " = " in line:
             k, v = line.strip().split(" = ", 1)
             vals[k] = v
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    if vals.get("kernel_source_sha256_16") != sha:
+    if vals.get("kernel_source_sha256_16") != jacobi_source_sha(kernel_t):
         return None
     return float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"])
 
@@ -356,7 +363,7 @@ def main():
         extra["small_64cubed"] = small_grids(P, torch)
     if "by_t" in sections:
         per_t = {}
-        for t in (1, 2, 4, 8, 16):
+        for t in (1, 2, 3, 4, 5, 6, 7, 8, 16):
             pl, _ = P.jacobi_plan(S, t)
             jacobi_run(P, torch, u, s, S, t)
             m = events_time(torch, lambda: jacobi_run(P, torch, u, s, S, t), reps=2) / 2
@@ -374,7 +381,7 @@ def main():
         u32 = u.float()
         s32 = torch.empty_like(u32)
         per32 = {}
-        for t in (1, 4, 8):
+        for t in (1, 2, 3, 4, 5, 6, 7, 8):
             jacobi_run(P, torch, u32, s32, S, t)
             m = events_time(torch, lambda: jacobi_run(P, torch, u32, s32, S, t), reps=2) / 2
             pl, _ = P.jacobi_plan(S, t, fp32=True)

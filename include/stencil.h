@@ -101,8 +101,9 @@ typedef struct {
  *  bc       ST_BC_KEEP: use u's ghost cells as given; ST_BC_CONST: first set
  *           every ghost cell of u to bc_value.
  *  sweeps   >= 0 (0 only applies bc).
- *  t_fuse   sweeps fused per pass: 0 = automatic, or 1, 2, 4, 8, 16.  A pass
- *           keeps at most 8 levels on chip; 16 runs as passes of 8.
+ *  t_fuse   sweeps fused per pass: 0 = automatic, or 1..8, or 16.  A pass
+ *           keeps at most 8 levels on chip; 16 runs as passes of 8.  Any
+ *           other value is ST_EINVAL.
  *  Result: bit-identical to `sweeps` sequential sweeps for every t_fuse.
  */
 int stencil_jacobi(const st_grid *grid, int32_t dtype, void *u, void *scratch, const void *f,
@@ -111,12 +112,15 @@ int stencil_jacobi(const st_grid *grid, int32_t dtype, void *u, void *scratch, c
 
 /*
  * stencil_jacobi_plan -- the pass schedule stencil_jacobi uses for
- * (dtype, sweeps, t_fuse): writes the number of kernel launches to *passes,
- * up to max_list per-pass fused-sweep counts to t_list (may be NULL), and
- * whether a final scratch->u copy is needed to *final_copy (may be NULL).
+ * (dtype, f != NULL, sweeps, t_fuse): writes the number of kernel launches to
+ * *passes, up to max_list per-pass fused-sweep counts to t_list (may be
+ * NULL), and whether a final scratch->u copy is needed to *final_copy (may be
+ * NULL).  has_rhs: nonzero when stencil_jacobi gets a right-hand side (the
+ * automatic depth differs).  Host-only; ST_EINVAL for a bad dtype, sweeps or
+ * t_fuse, or passes == NULL.
  */
-int stencil_jacobi_plan(int32_t dtype, int32_t sweeps, int32_t t_fuse, int32_t *passes,
-                        int32_t *t_list, int32_t max_list, int32_t *final_copy);
+int stencil_jacobi_plan(int32_t dtype, int32_t has_rhs, int32_t sweeps, int32_t t_fuse,
+                        int32_t *passes, int32_t *t_list, int32_t max_list, int32_t *final_copy);
 
 /*
  * stencil_gs -- `sweeps` in-place lexicographic Gauss-Seidel sweeps
@@ -124,8 +128,9 @@ int stencil_jacobi_plan(int32_t dtype, int32_t sweeps, int32_t t_fuse, int32_t *
  * and temporal-wavefront schemes of Sec. 3/4 re-expressed as bundles of
  * x-lines scheduled in topological order with per-bundle progress counters
  * instead of barriers.  t_fuse sweeps are in flight per launch (0 = all
- * sweeps in one launch; 1 = one launch per sweep).  Bit-identical to the
- * sequential loop nest.  Uses an internal flag buffer owned by the library.
+ * sweeps in one launch; 1 = one launch per sweep; 1..8 or 16 accepted).
+ * Bit-identical to the sequential loop nest.  Uses an internal flag buffer
+ * owned by the library.
  * Same argument meanings as stencil_jacobi.
  */
 int stencil_gs(const st_grid *grid, int32_t dtype, void *u, const void *f, const st_weights *w,
@@ -158,7 +163,8 @@ int stencil_residual(const st_grid *grid, const double *u, const double *fp, dou
  *  method      0 = Jacobi, 1 = Gauss-Seidel.
  *  u           FP64 grid: initial guess in, solution out; ghosts = Dirichlet.
  *  fp          interior-only FP64 right-hand side (h^2 f).
- *  t_fuse      fused sweeps per pass of the inner smoother (0 = automatic).
+ *  t_fuse      fused sweeps per pass of the inner smoother (0 = automatic,
+ *              else 1..8 or 16 as for stencil_jacobi).
  *  max_outer   residual checks followed by smoothing allowed; ST_ENOCONV if
  *              rel_tol is not reached after max_outer of them.
  *  outer_done, rel_res_out  (host pointers, may be NULL): smoothing rounds

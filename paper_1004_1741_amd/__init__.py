@@ -77,7 +77,7 @@ _P = ctypes.POINTER
 _vp, _i32, _i64, _dbl, _u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64
 SIGNATURES = [
     ("stencil_jacobi", _i32, [_P(Grid), _i32, _vp, _vp, _vp, _P(Weights), _i32, _dbl, _i32, _i32, _vp]),
-    ("stencil_jacobi_plan", _i32, [_i32, _i32, _i32, _P(_i32), _P(_i32), _i32, _P(_i32)]),
+    ("stencil_jacobi_plan", _i32, [_i32, _i32, _i32, _i32, _P(_i32), _P(_i32), _i32, _P(_i32)]),
     ("stencil_gs", _i32, [_P(Grid), _i32, _vp, _vp, _P(Weights), _i32, _dbl, _i32, _i32, _vp]),
     ("stencil_residual", _i32, [_P(Grid), _vp, _vp, _vp, _P(_dbl), _vp]),
     ("stencil_refine_solve", _i32, [_P(Grid), _i32, _i32, _vp, _vp, _i32, _i32, _dbl, _i32,
@@ -175,12 +175,13 @@ def jacobi(u, scratch, sweeps, a=0.0, b=1.0 / 6.0, f=None, g=0.0, t_fuse=0, halo
     return u
 
 
-def jacobi_plan(sweeps, t_fuse=0, fp32=False):
+def jacobi_plan(sweeps, t_fuse=0, fp32=False, rhs=False):
     n = ctypes.c_int32(0)
     fc = ctypes.c_int32(0)
     buf = (ctypes.c_int32 * max(1, sweeps))()
-    _check(lib().stencil_jacobi_plan(ST.FP32 if fp32 else ST.FP64, int(sweeps), int(t_fuse),
-                                     ctypes.byref(n), buf, len(buf), ctypes.byref(fc)))
+    _check(lib().stencil_jacobi_plan(ST.FP32 if fp32 else ST.FP64, int(bool(rhs)), int(sweeps),
+                                     int(t_fuse), ctypes.byref(n), buf, len(buf),
+                                     ctypes.byref(fc)))
     return list(buf[:n.value]), bool(fc.value)
 
 

@@ -56,6 +56,19 @@ hipError_t launch_jacobi_batch(bool fp32, int tb, bool has_a, bool has_f,
                                const std::vector<JacBatchItem> &items, void *table_dev,
                                std::vector<unsigned char> &host_buf, hipStream_t s);
 
+// The fused pass for one level count TB (1..8); each TB is compiled in its
+// own translation unit, the functions above dispatch on tb.
+template <int TB>
+struct JacobiLevels {
+    static JacTileCfg cfg(bool fp32);
+    static hipError_t pass(bool fp32, const Geom &g, const void *src, void *dst, const void *f,
+                           double a, double b, double gw, int zc, hipStream_t s);
+    static hipError_t batch(bool fp32, bool has_a, bool has_f,
+                            const std::vector<JacBatchItem> &items, void *table_dev,
+                            std::vector<unsigned char> &host_buf, hipStream_t s);
+    static size_t table_bytes(int njobs);
+};
+
 // Ghost-layer helpers (all ghost cells of a padded grid).
 hipError_t launch_fill_ghosts(bool fp32, const Geom &g, void *u, double value, hipStream_t s);
 hipError_t launch_copy_ghosts(bool fp32, const Geom &g, const void *src, void *dst,

@@ -1,701 +1,65 @@
-// jacobi.hip -- fused multi-sweep Jacobi pass (gfx950).
-//
-// Method (Sec. 3 Jacobi loop nest; Sec. 4 temporal wavefront blocking):
-// TB consecutive Jacobi sweeps are applied in ONE pass over HBM.  The paper
-// gives each of t threads sharing a cache one sweep, shifted in z, with a
-// barrier after every plane.  Here one workgroup owns an x-y tile of the grid
-// and marches it through z; the TB time levels of the tile live on chip:
-//
-//   * a wave covers 64*VX consecutive x sites (16-byte vector loads) and RY
-//     rows; NW waves stack in y, so a tile is (64*VX) x (NW*RY) sites;
-//   * level tau of plane p needs level tau-1 at planes p-1, p, p+1.  With a
-//     skew of one plane per level, step s loads plane s of level 0 and
-//     produces plane s-tau of level tau; the z-1 neighbour stays in a
-//     register ("prev") and the in-plane part of the sum is formed one step
-//     early ("q"), so each level keeps two planes in registers;
-//   * x neighbours come from adjacent lanes through DPP wave shifts, y
-//     neighbours from the thread's own rows or, at wave edges, through a
-//     small double-buffered LDS exchange (one barrier per level per step);
-//   * tiles overlap by TB sites on each side (the dependency cone), so only
-//     the centre (64*VX - 2*TB - VX + 1) x (NW*RY - 2*TB) sites are stored;
-//     ghost cells inside a tile keep their Dirichlet value at every level;
-//   * z is split into chunks; a chunk starts TB planes early to fill the
-//     pipeline (or at the ghost plane, where all levels are known).
-//
-// HBM sees one load of level 0 and one store of level TB per site per pass:
-// 2*sizeof(T) bytes per site per TB sweeps (Eq. (1) with the traffic divided
-// by the number of fused sweeps).  All arithmetic keeps the canonical order
-//   s = ((((x- + x+) + y-) + y+) + z-) + z+,  v = (a*c) + (b*s) [+ g*f]
-// without FMA contraction, so every TB gives results bit-identical to TB
-// sequential sweeps.
-#include <type_traits>
-
+// jacobi.hip -- dispatch of the fused Jacobi pass over the level count TB.
+// The kernels and launchers are in jacobi_impl.h; each TB is compiled in
+// jacobi_t<TB>.hip.
 #include "internal.h"
 
-#pragma clang fp contract(off)
-
 namespace stk {
-namespace {
 
-template <typename T, int VX>
-struct VecT;
-template <>
-struct VecT<double, 2> {
-    typedef double type __attribute__((ext_vector_type(2), aligned(8)));
-};
-template <>
-struct VecT<float, 4> {
-    typedef float type __attribute__((ext_vector_type(4), aligned(4)));
-};
-template <>
-struct VecT<float, 2> {
-    typedef float type __attribute__((ext_vector_type(2), aligned(4)));
-};
-
-__device__ __forceinline__ float from_lower_lane(float v) {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xf, 0xf, true));
-}
-__device__ __forceinline__ float from_upper_lane(float v) {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
-}
-__device__ __forceinline__ double from_lower_lane(double v) {
-    int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x138, 0xf, 0xf, true);
-    int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x138, 0xf, 0xf, true);
-    return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ double from_upper_lane(double v) {
-    int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x130, 0xf, 0xf, true);
-    int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x130, 0xf, 0xf, true);
-    return __hiloint2double(hi, lo);
-}
-
-template <typename T>
-struct JacArgs {
-    const T *src;
-    T *dst;
-    const T *f;      // interior-only right-hand side or nullptr
-    int64_t px;      // row pitch (elements)
-    int64_t plane;   // plane pitch (elements)
-    int nx, ny, nz, h;
-    T a, b, g;
-    int tiles_x, tiles_y, nchunks, zc, ow, oh, ntiles;
-};
-
-template <typename T, int VX, bool EDGE>
-__device__ __forceinline__ void load_row(const T *__restrict__ p, unsigned okmask, T (&out)[VX]) {
-    if constexpr (!EDGE && (VX * sizeof(T) == 16 || (VX == 2 && sizeof(T) == 4))) {
-        typedef typename VecT<T, VX>::type V;
-        V v = *reinterpret_cast<const V *>(p);
-#pragma unroll
-        for (int i = 0; i < VX; ++i) out[i] = v[i];
-    } else if constexpr (!EDGE) {
-#pragma unroll
-        for (int i = 0; i < VX; ++i) out[i] = p[i];
-    } else {
-#pragma unroll
-        for (int i = 0; i < VX; ++i) out[i] = (okmask >> i & 1u) ? p[i] : T(0);
-    }
-}
-
-template <typename T, int VX>
-__device__ __forceinline__ void store_row(T *__restrict__ p, unsigned mask, const T (&v)[VX]) {
-    constexpr unsigned full = (1u << VX) - 1u;
-    if constexpr (VX * sizeof(T) == 16 || (VX == 2 && sizeof(T) == 4)) {
-        if (mask == full) {
-            typedef typename VecT<T, VX>::type V;
-            V w;
-#pragma unroll
-            for (int i = 0; i < VX; ++i) w[i] = v[i];
-            *reinterpret_cast<V *>(p) = w;
-            return;
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < VX; ++i)
-        if (mask >> i & 1u) p[i] = v[i];
-}
-
-// Right-hand side ring: each thread keeps the f values of its own sites for
-// planes s-2 .. s-TB (needed by levels 2..TB at step s) in LDS, so f is read
-// from memory once per pass instead of once per level.  Used where it fits
-// next to the exchange buffer in the 160 KB of LDS.
-template <typename T, int TB, int VX, int RY, int NW, bool HAS_F>
-struct FRing {
-    static constexpr size_t xch_bytes = (size_t)2 * TB * NW * 2 * 64 * VX * sizeof(T);
-    static constexpr size_t ring_elems = (size_t)(TB > 1 ? TB - 1 : 0) * RY * VX * NW * 64;
-    static constexpr bool on =
-        HAS_F && TB >= 2 && xch_bytes + ring_elems * sizeof(T) <= 160 * 1024;
-    static constexpr size_t alloc = on ? ring_elems : 1;
-};
-
-template <typename T, int TB, int VX, int RY, int NW, bool HAS_A, bool HAS_F, bool EDGE>
-__device__ __forceinline__ void jacobi_tile(const JacArgs<T> &A, int tx, int ty, int cz,
-                                            T (*xch)[TB][NW][2][64 * VX], T *fring) {
-    constexpr bool RING = FRing<T, TB, VX, RY, NW, HAS_F>::on;
-    // level 1 takes f from registers loaded one step early when the ring is
-    // used; otherwise every level loads its own f plane
-    constexpr bool FPRE = RING;
-    const int lane = threadIdx.x & 63;
-    const int w = threadIdx.x >> 6;
-    const int h = A.h;
-
-    // ---- tile geometry (padded coordinates) ----
-    const int ox0 = h + tx * A.ow;
-    const int ox1 = min(ox0 + A.ow, h + A.nx);
-    int xs = ox0 - TB;
-    xs -= ((xs % VX) + VX) % VX;  // align the tile start to the vector width
-    const int oy0 = h + ty * A.oh;
-    const int oy1 = min(oy0 + A.oh, h + A.ny);
-    const int ys = oy0 - TB;
-    const int z0 = h + cz * A.zc;
-    const int z1 = min(z0 + A.zc, h + A.nz);
-    int zb = z0 - TB;
-    if (zb < h - 1) zb = h - 1;          // never below the ghost plane
-    int ze = z1 - 1 + TB;
-    bool top_bnd = false;
-    if (ze >= h + A.nz) { ze = h + A.nz; top_bnd = true; }  // ghost plane on top
-
-    const int x0 = xs + lane * VX;  // this lane's first x
-    const int y0 = ys + w * RY;     // this wave's first row
-
-    // ---- per-thread masks ----
-    unsigned ldx = 0, updx = 0, stx = 0, ldy = 0, updy = 0, sty = 0;
-#pragma unroll
-    for (int v = 0; v < VX; ++v) {
-        const int x = x0 + v;
-        ldx |= (x >= 0 && x < A.nx + 2 * h) ? (1u << v) : 0u;
-        updx |= (x >= h && x < h + A.nx) ? (1u << v) : 0u;
-        stx |= (x >= ox0 && x < ox1) ? (1u << v) : 0u;
-    }
-#pragma unroll
-    for (int r = 0; r < RY; ++r) {
-        const int y = y0 + r;
-        ldy |= (y >= 0 && y < A.ny + 2 * h) ? (1u << r) : 0u;
-        updy |= (y >= h && y < h + A.ny) ? (1u << r) : 0u;
-        sty |= (y >= oy0 && y < oy1) ? (1u << r) : 0u;
-    }
-    // element offset of (row r, x0) within a plane; rows outside the array are
-    // never dereferenced (EDGE masks), so clamping them keeps offsets sane.
-    int rowoff[RY];
-#pragma unroll
-    for (int r = 0; r < RY; ++r) {
-        int y = y0 + r;
-        if (EDGE) y = min(max(y, 0), A.ny + 2 * h - 1);
-        rowoff[r] = y * (int)A.px + x0;
-    }
-
-    auto load_plane = [&](int z, T (&out)[RY][VX]) {
-        const T *base = A.src + (int64_t)z * A.plane;
-#pragma unroll
-        for (int r = 0; r < RY; ++r) {
-            const unsigned ok = (ldy >> r & 1u) ? ldx : 0u;
-            load_row<T, VX, EDGE>(base + rowoff[r], ok, out[r]);
-        }
-    };
-    auto load_f = [&](int z, T (&out)[RY][VX]) {
-        // f is interior-only: f[((z-h)*ny + (y-h))*nx + (x-h)].  Planes
-        // outside the interior (only read by levels that copy there) are
-        // clamped to a valid plane.
-        const int zc = min(max(z, h), h + A.nz - 1);
-        const T *base = A.f + ((int64_t)(zc - h) * A.ny) * A.nx;
-#pragma unroll
-        for (int r = 0; r < RY; ++r) {
-            const unsigned ok = (updy >> r & 1u) ? updx : 0u;
-            const int y = EDGE ? min(max(y0 + r, h), h + A.ny - 1) : y0 + r;
-            load_row<T, VX, EDGE>(base + (int64_t)(y - h) * A.nx + (x0 - h), ok, out[r]);
-        }
-    };
-
-    // Two planes per level live in registers, in arrays P0 and P1 whose roles
-    // alternate from step to step.  At the start of step s, "A" holds
-    // A[k] = L_k[s-k-1] (newest plane of level k) and "B" holds
-    // B[k] = L_k[s-k-2]; the edge rows of every A[k] were exchanged through
-    // LDS at the end of the previous step.  Level tau at plane p = s-tau needs
-    // A[tau-1] (centre and in-plane neighbours), B[tau-1][site] (z-) and the
-    // new plane of level tau-1 at the same site (z+); once read, B[tau-1][site]
-    // is dead and is overwritten by that new plane, so after the step the "B"
-    // array holds the newest planes and the roles swap -- no register moves.
-    T P0[TB][RY][VX];
-    T P1[TB][RY][VX];
-    T nxt[RY][VX];
-    // f of plane s-1 (for level 1 at step s) and of plane s (loaded at step s),
-    // alternating like P0/P1
-    T F0[FPRE ? RY : 1][VX];
-    T F1[FPRE ? RY : 1][VX];
-    const int tid = threadIdx.x;
-    auto ring_slot = [&](int plane) {
-        constexpr int M = TB > 1 ? TB - 1 : 1;
-        return ((plane % M) + M) % M;
-    };
-    auto ring_at = [&](int slot, int r, int v) -> T & {
-        return fring[((slot * RY + r) * VX + v) * (NW * 64) + tid];
-    };
-
-    auto exchange = [&](int buf, T (&Anew)[TB][RY][VX]) {
-        if constexpr (NW > 1) {
-#pragma unroll
-            for (int k = 0; k < TB; ++k) {
-                T *x0 = &xch[buf][k][w][0][lane * VX];
-                T *x1 = &xch[buf][k][w][1][lane * VX];
-#pragma unroll
-                for (int v = 0; v < VX; ++v) x0[v] = Anew[k][0][v], x1[v] = Anew[k][RY - 1][v];
-            }
-        }
-        __syncthreads();
-    };
-
-    // prologue: plane zb is known at every level (ghost plane, or a warm-up
-    // plane whose levels never reach a stored output)
-    load_plane(zb, nxt);
-#pragma unroll
-    for (int k = 0; k < TB; ++k)
-#pragma unroll
-        for (int r = 0; r < RY; ++r)
-#pragma unroll
-            for (int v = 0; v < VX; ++v) P0[k][r][v] = nxt[r][v], P1[k][r][v] = nxt[r][v];
-    if (zb + 1 <= ze) load_plane(zb + 1, nxt);
-    if constexpr (FPRE) load_f(zb, F0);
-    int buf = 0;
-    exchange(buf, P0);
-    const int s_end = z1 - 1 + TB;
-
-    // FULL: steady state, every level produces and the next plane exists
-    auto step = [&](int s, T (&Aa)[TB][RY][VX], T (&Bb)[TB][RY][VX],
-                    T (&Fc)[FPRE ? RY : 1][VX], T (&Fn)[FPRE ? RY : 1][VX], auto full_c) {
-        constexpr bool FULL = decltype(full_c)::value;
-        T Nprev[RY][VX];  // new plane of level tau-1 (level 0: plane s, loaded)
-#pragma unroll
-        for (int r = 0; r < RY; ++r)
-#pragma unroll
-            for (int v = 0; v < VX; ++v) Nprev[r][v] = nxt[r][v];
-        if (FULL || s + 1 <= ze) load_plane(s + 1, nxt);
-        if constexpr (FPRE) load_f(s, Fn);  // for level 1 at step s+1
-
-#pragma unroll
-        for (int tau = 1; tau <= TB; ++tau) {
-            const int p = s - tau;  // plane of level tau produced now
-            const int ce = top_bnd ? ze - 1 : ze - tau;
-            // Planes outside [zb+1, ce] take the value of the level below:
-            // ghost planes keep their Dirichlet value, elsewhere the value is
-            // never used.
-            const bool inr = FULL || (p >= zb + 1 && p <= ce);
-            T Ncur[RY][VX];
-            auto update = [&]() {
-                // in-plane neighbours of L_{tau-1}[p] = Aa[tau-1]
-                T lft[RY], rgt[RY], ytop[VX], ybot[VX];
-#pragma unroll
-                for (int r = 0; r < RY; ++r) {
-                    lft[r] = from_lower_lane(Aa[tau - 1][r][VX - 1]);
-                    rgt[r] = from_upper_lane(Aa[tau - 1][r][0]);
-                }
-                if constexpr (NW > 1) {
-                    const T *up = &xch[buf][tau - 1][w > 0 ? w - 1 : w][1][lane * VX];
-                    const T *dn = &xch[buf][tau - 1][w < NW - 1 ? w + 1 : w][0][lane * VX];
-#pragma unroll
-                    for (int v = 0; v < VX; ++v) ytop[v] = up[v], ybot[v] = dn[v];
-                } else {
-#pragma unroll
-                    for (int v = 0; v < VX; ++v)
-                        ytop[v] = Aa[tau - 1][0][v], ybot[v] = Aa[tau - 1][RY - 1][v];
-                }
-                T fv[HAS_F ? RY : 1][VX];
-                if constexpr (HAS_F) {
-                    if (FPRE && tau == 1) {
-#pragma unroll
-                        for (int r = 0; r < RY; ++r)
-#pragma unroll
-                            for (int v = 0; v < VX; ++v) fv[r][v] = Fc[FPRE ? r : 0][v];
-                    } else if constexpr (RING) {
-                        const int sl = ring_slot(p);
-#pragma unroll
-                        for (int r = 0; r < RY; ++r)
-#pragma unroll
-                            for (int v = 0; v < VX; ++v) fv[r][v] = ring_at(sl, r, v);
-                    } else if (inr) {
-                        load_f(p, fv);
-                    } else {
-#pragma unroll
-                        for (int r = 0; r < RY; ++r)
-#pragma unroll
-                            for (int v = 0; v < VX; ++v) fv[r][v] = T(0);
-                    }
-                }
-#pragma unroll
-                for (int r = 0; r < RY; ++r)
-#pragma unroll
-                    for (int v = 0; v < VX; ++v) {
-                        const T c = Aa[tau - 1][r][v];
-                        const T xm = (v > 0) ? Aa[tau - 1][r][v - 1] : lft[r];
-                        const T xp = (v < VX - 1) ? Aa[tau - 1][r][v + 1] : rgt[r];
-                        const T ym = (r > 0) ? Aa[tau - 1][r - 1][v] : ytop[v];
-                        const T yp = (r < RY - 1) ? Aa[tau - 1][r + 1][v] : ybot[v];
-                        const T sum =
-                            ((((xm + xp) + ym) + yp) + Bb[tau - 1][r][v]) + Nprev[r][v];
-                        T val;
-                        if constexpr (HAS_A)
-                            val = (A.a * c) + (A.b * sum);
-                        else
-                            val = A.b * sum;
-                        if constexpr (HAS_F) val = val + (A.g * fv[r][v]);
-                        if constexpr (EDGE) {
-                            const bool up = (updy >> r & 1u) && (updx >> v & 1u);
-                            val = up ? val : c;
-                        }
-                        Ncur[r][v] = val;
-                        Bb[tau - 1][r][v] = Nprev[r][v];
-                    }
-            };
-            auto copy_below = [&]() {
-#pragma unroll
-                for (int r = 0; r < RY; ++r)
-#pragma unroll
-                    for (int v = 0; v < VX; ++v) {
-                        Ncur[r][v] = Aa[tau - 1][r][v];
-                        Bb[tau - 1][r][v] = Nprev[r][v];
-                    }
-            };
-            if constexpr (TB >= 2) {
-                // The update runs on every step (it reads only registers and
-                // LDS) and the few fill/drain steps overwrite it afterwards: the
-                // common path then carries no register copies.  (Measured: this
-                // is faster for TB >= 2 and slower for TB = 1.)
-                update();
-                if (__builtin_expect(!inr, 0)) copy_below();
-            } else {
-                if (inr)
-                    update();
-                else
-                    copy_below();
-            }
-#pragma unroll
-            for (int r = 0; r < RY; ++r)
-#pragma unroll
-                for (int v = 0; v < VX; ++v) Nprev[r][v] = Ncur[r][v];
-        }
-        // plane s-1 of f joins the ring, in the slot of plane s-TB (read by
-        // level TB above: each thread only touches its own entries, in order)
-        if constexpr (RING) {
-            const int sl = ring_slot(s - 1);
-#pragma unroll
-            for (int r = 0; r < RY; ++r)
-#pragma unroll
-                for (int v = 0; v < VX; ++v) ring_at(sl, r, v) = Fc[r][v];
-        }
-        // store level TB of plane s-TB
-        const int p = s - TB;
-        if (p >= z0 && p < z1) {
-            T *base = A.dst + (int64_t)p * A.plane;
-#pragma unroll
-            for (int r = 0; r < RY; ++r)
-                if (sty >> r & 1u) store_row<T, VX>(base + rowoff[r], stx, Nprev[r]);
-        }
-        buf ^= 1;
-        exchange(buf, Bb);
-    };
-
-    using Part = std::integral_constant<bool, false>;
-    int s = zb + 1;
-    for (; s + 1 <= s_end; s += 2) {
-        step(s, P0, P1, F0, F1, Part{});
-        step(s + 1, P1, P0, F1, F0, Part{});
-    }
-    if (s <= s_end) step(s, P0, P1, F0, F1, Part{});
-}
-
-template <typename T, int TB, int VX, int RY, int NW, bool HAS_A, bool HAS_F>
-__global__ void __launch_bounds__(NW * 64) jacobi_pass_kernel(JacArgs<T> A) {
-    __shared__ T xch[2][TB][NW][2][64 * VX];
-    __shared__ T fring[FRing<T, TB, VX, RY, NW, HAS_F>::alloc];
-    // The dispatcher places consecutive workgroup ids round-robin on the 8
-    // XCDs; give each XCD a contiguous range of tiles so that neighbouring
-    // tiles (which re-read each other's overlap) share an L2.
-    const int G = gridDim.x;
-    const int per = G >> 3;
-    const int bid = blockIdx.x;
-    const int l = (bid & 7) * per + (bid >> 3);
-    if (l >= A.ntiles) return;
-    const int tpc = A.tiles_x * A.tiles_y;
-    const int cz = l / tpc;
-    const int rem = l - cz * tpc;
-    const int ty = rem / A.tiles_x;
-    const int tx = rem - ty * A.tiles_x;
-
-    // interior tile: the whole loaded footprint lies inside the interior
-    const int ox0 = A.h + tx * A.ow;
-    int xs = ox0 - TB;
-    xs -= ((xs % VX) + VX) % VX;
-    const int ys = A.h + ty * A.oh - TB;
-    const bool interior = xs >= A.h && xs + 64 * VX <= A.h + A.nx && ys >= A.h &&
-                          ys + NW * RY <= A.h + A.ny;
-    if (interior)
-        jacobi_tile<T, TB, VX, RY, NW, HAS_A, HAS_F, false>(A, tx, ty, cz, xch, fring);
-    else
-        jacobi_tile<T, TB, VX, RY, NW, HAS_A, HAS_F, true>(A, tx, ty, cz, xch, fring);
-}
-
-// Batched pass: one launch advances several independent grids (jobs of the
-// job service) by one fused pass each.  jobs[j].wg_begin is the prefix sum of
-// the workgroups of the jobs before j; a workgroup finds its job by binary
-// search and then runs exactly the single-grid tile code, so a job's result
-// does not depend on which other jobs share the launch.
-template <typename T>
-struct JacJob {
-    JacArgs<T> a;
-    int wg_begin;
-    int pad_[3];
-};
-
-template <typename T, int TB, int VX, int RY, int NW, bool HAS_A, bool HAS_F>
-__global__ void __launch_bounds__(NW * 64)
-    jacobi_batch_kernel(const JacJob<T> *__restrict__ jobs, int njobs, int total) {
-    __shared__ T xch[2][TB][NW][2][64 * VX];
-    __shared__ T fring[FRing<T, TB, VX, RY, NW, HAS_F>::alloc];
-    const int G = gridDim.x;
-    const int per = G >> 3;
-    const int bid = blockIdx.x;
-    const int l = (bid & 7) * per + (bid >> 3);
-    if (l >= total) return;
-    int lo = 0, hi = njobs - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (jobs[mid].wg_begin <= l) lo = mid; else hi = mid - 1;
-    }
-    const JacArgs<T> A = jobs[lo].a;
-    const int li = l - jobs[lo].wg_begin;
-    const int tpc = A.tiles_x * A.tiles_y;
-    const int cz = li / tpc;
-    const int rem = li - cz * tpc;
-    const int ty = rem / A.tiles_x;
-    const int tx = rem - ty * A.tiles_x;
-    const int ox0 = A.h + tx * A.ow;
-    int xs = ox0 - TB;
-    xs -= ((xs % VX) + VX) % VX;
-    const int ys = A.h + ty * A.oh - TB;
-    const bool interior = xs >= A.h && xs + 64 * VX <= A.h + A.nx && ys >= A.h &&
-                          ys + NW * RY <= A.h + A.ny;
-    if (interior)
-        jacobi_tile<T, TB, VX, RY, NW, HAS_A, HAS_F, false>(A, tx, ty, cz, xch, fring);
-    else
-        jacobi_tile<T, TB, VX, RY, NW, HAS_A, HAS_F, true>(A, tx, ty, cz, xch, fring);
-}
-
-// Tile configurations (VX, RY, NW), chosen by measurement on MI355X among
-// shapes that fit the register file: per thread about (2*TB + 3) * RY * VX
-// values stay live, which must fit 256 VGPRs (two waves per SIMD), while the
-// tile must be large against the 2*TB overlap on each side.
-template <typename T, int TB>
-struct CfgBase;
-template <> struct CfgBase<double, 1> { static constexpr int VX = 2, RY = 4, NW = 8; };
-template <> struct CfgBase<double, 2> { static constexpr int VX = 2, RY = 4, NW = 8; };
-template <> struct CfgBase<double, 4> { static constexpr int VX = 1, RY = 8, NW = 8; };
-template <> struct CfgBase<double, 8> { static constexpr int VX = 1, RY = 5, NW = 8; };
-template <> struct CfgBase<float, 1> { static constexpr int VX = 2, RY = 8, NW = 8; };
-template <> struct CfgBase<float, 2> { static constexpr int VX = 2, RY = 8, NW = 8; };
-template <> struct CfgBase<float, 4> { static constexpr int VX = 2, RY = 6, NW = 8; };
-template <> struct CfgBase<float, 8> { static constexpr int VX = 1, RY = 8, NW = 8; };
-// With a right-hand side the prefetched f planes add register pressure and
-// the f ring needs LDS next to the exchange buffer: some shapes are shorter
-// (FP32 t=8 also so that its ring fits; FP64 t=8 has no room for the ring
-// and loads f per level).
-template <typename T, int TB, bool HAS_F>
-struct Cfg : CfgBase<T, TB> {};
-template <> struct Cfg<double, 4, true> { static constexpr int VX = 1, RY = 6, NW = 8; };
-template <> struct Cfg<double, 8, true> { static constexpr int VX = 1, RY = 4, NW = 8; };
-template <> struct Cfg<float, 8, true> { static constexpr int VX = 1, RY = 6, NW = 8; };
-
-template <typename T, int TB, bool HAS_F = false>
-JacTileCfg cfg_of() {
-    return JacTileCfg{TB, Cfg<T, TB, HAS_F>::VX, Cfg<T, TB, HAS_F>::RY, Cfg<T, TB, HAS_F>::NW};
-}
-
-// Number of z-chunks.  Every chunk re-computes TB warm-up planes (and some
-// fill/drain steps), while the grid runs in rounds of `resident` workgroups:
-// pick the count that minimises rounds * (planes per chunk + fill).
-int choose_chunks(const JacTileCfg &c, const Geom &g, int tiles_xy, int resident) {
-    if (resident < 1) resident = 256;
-    int best = 1;
-    double best_cost = 1e300;
-    const int maxch = g.nz / 8 > 1 ? g.nz / 8 : 1;
-    for (int nch = 1; nch <= maxch; ++nch) {
-        const int zc = (g.nz + nch - 1) / nch;
-        const long wgs = (long)tiles_xy * nch;
-        const long rounds = (wgs + resident - 1) / resident;
-        const double cost = (double)rounds * (zc + c.tb + 1);
-        if (cost < best_cost - 1e-9) {
-            best_cost = cost;
-            best = nch;
-        }
-    }
-    return best;
-}
-
-template <typename T, int TB, bool HAS_A, bool HAS_F>
-int resident_wgs(bool batch) {
-    using C = Cfg<T, TB, HAS_F>;
-    static int cached[2] = {0, 0};
-    int &r = cached[batch ? 1 : 0];
-    if (r == 0) {
-        int per_cu = 0, dev = 0, ncu = 0;
-        const void *kfn =
-            batch ? reinterpret_cast<const void *>(
-                        jacobi_batch_kernel<T, TB, C::VX, C::RY, C::NW, HAS_A, HAS_F>)
-                  : reinterpret_cast<const void *>(
-                        jacobi_pass_kernel<T, TB, C::VX, C::RY, C::NW, HAS_A, HAS_F>);
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, C::NW * 64, 0) !=
-                hipSuccess || per_cu < 1)
-            per_cu = 1;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) !=
-                hipSuccess || ncu < 1)
-            ncu = 256;
-        r = per_cu * ncu;
-    }
-    return r;
-}
-
-template <typename T, int TB, bool HAS_F>
-JacArgs<T> make_args(const Geom &g, const void *src, void *dst, const void *f, double a,
-                     double b, double gw, int zc, int resident) {
-    const JacTileCfg c = cfg_of<T, TB, HAS_F>();
-    JacArgs<T> A;
-    A.src = static_cast<const T *>(src);
-    A.dst = static_cast<T *>(dst);
-    A.f = static_cast<const T *>(f);
-    A.px = g.px;
-    A.plane = g.plane();
-    A.nx = g.nx; A.ny = g.ny; A.nz = g.nz; A.h = g.h;
-    A.a = (T)a; A.b = (T)b; A.g = (T)gw;
-    A.ow = c.ow();
-    A.oh = c.oh();
-    A.tiles_x = (g.nx + A.ow - 1) / A.ow;
-    A.tiles_y = (g.ny + A.oh - 1) / A.oh;
-    const int tiles_xy = A.tiles_x * A.tiles_y;
-    if (zc <= 0) {
-        const int nch = choose_chunks(c, g, tiles_xy, resident);
-        zc = (g.nz + nch - 1) / nch;
-    }
-    A.zc = zc;
-    A.nchunks = (g.nz + zc - 1) / zc;
-    A.ntiles = tiles_xy * A.nchunks;
-    return A;
-}
-
-template <typename T, int TB, bool HAS_A, bool HAS_F>
-hipError_t launch_t(const Geom &g, const void *src, void *dst, const void *f, double a, double b,
-                    double gw, int zc, hipStream_t s) {
-    using C = Cfg<T, TB, HAS_F>;
-    const JacArgs<T> A = make_args<T, TB, HAS_F>(g, src, dst, f, a, b, gw, zc,
-                                          resident_wgs<T, TB, HAS_A, HAS_F>(false));
-    const int grid = ((A.ntiles + 7) / 8) * 8;
-    hipLaunchKernelGGL((jacobi_pass_kernel<T, TB, C::VX, C::RY, C::NW, HAS_A, HAS_F>),
-                       dim3(grid), dim3(C::NW * 64), 0, s, A);
-    return hipGetLastError();
-}
-
-template <typename T, int TB, bool HAS_A, bool HAS_F>
-hipError_t launch_batch_t(const std::vector<JacBatchItem> &items, void *table_dev,
-                          std::vector<unsigned char> &host_buf, hipStream_t s) {
-    using C = Cfg<T, TB, HAS_F>;
-    const int resident = resident_wgs<T, TB, HAS_A, HAS_F>(true);
-    host_buf.resize(items.size() * sizeof(JacJob<T>));
-    JacJob<T> *jobs = reinterpret_cast<JacJob<T> *>(host_buf.data());
-    int total = 0;
-    for (size_t j = 0; j < items.size(); ++j) {
-        const JacBatchItem &it = items[j];
-        jobs[j].a = make_args<T, TB, HAS_F>(it.g, it.src, it.dst, it.f, it.a, it.b, it.gw, 0, resident);
-        jobs[j].wg_begin = total;
-        total += jobs[j].a.ntiles;
-    }
-    hipError_t e = hipMemcpyAsync(table_dev, jobs, items.size() * sizeof(JacJob<T>),
-                                  hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return e;
-    const int grid = ((total + 7) / 8) * 8;
-    hipLaunchKernelGGL((jacobi_batch_kernel<T, TB, C::VX, C::RY, C::NW, HAS_A, HAS_F>),
-                       dim3(grid), dim3(C::NW * 64), 0, s,
-                       static_cast<const JacJob<T> *>(table_dev), (int)items.size(), total);
-    return hipGetLastError();
-}
-
-template <typename T, int TB>
-hipError_t launch_batch_tb(bool ha, bool hf, const std::vector<JacBatchItem> &items,
-                           void *table_dev, std::vector<unsigned char> &hb, hipStream_t s) {
-    if (ha && hf) return launch_batch_t<T, TB, true, true>(items, table_dev, hb, s);
-    if (ha) return launch_batch_t<T, TB, true, false>(items, table_dev, hb, s);
-    if (hf) return launch_batch_t<T, TB, false, true>(items, table_dev, hb, s);
-    return launch_batch_t<T, TB, false, false>(items, table_dev, hb, s);
-}
-
-template <typename T>
-hipError_t launch_batch_any(int tb, bool ha, bool hf, const std::vector<JacBatchItem> &items,
-                            void *table_dev, std::vector<unsigned char> &hb, hipStream_t s) {
-    switch (tb) {
-        case 1: return launch_batch_tb<T, 1>(ha, hf, items, table_dev, hb, s);
-        case 2: return launch_batch_tb<T, 2>(ha, hf, items, table_dev, hb, s);
-        case 4: return launch_batch_tb<T, 4>(ha, hf, items, table_dev, hb, s);
-        case 8: return launch_batch_tb<T, 8>(ha, hf, items, table_dev, hb, s);
-        default: return hipErrorInvalidValue;
-    }
-}
-
-template <typename T, int TB>
-hipError_t launch_tb(const Geom &g, const void *src, void *dst, const void *f, double a,
-                     double b, double gw, int zc, hipStream_t s) {
-    const bool ha = (a != 0.0), hf = (f != nullptr);
-    if (ha && hf) return launch_t<T, TB, true, true>(g, src, dst, f, a, b, gw, zc, s);
-    if (ha) return launch_t<T, TB, true, false>(g, src, dst, f, a, b, gw, zc, s);
-    if (hf) return launch_t<T, TB, false, true>(g, src, dst, f, a, b, gw, zc, s);
-    return launch_t<T, TB, false, false>(g, src, dst, f, a, b, gw, zc, s);
-}
-
-template <typename T>
-hipError_t launch_any(int tb, const Geom &g, const void *src, void *dst, const void *f, double a,
-                      double b, double gw, int zc, hipStream_t s) {
-    switch (tb) {
-        case 1: return launch_tb<T, 1>(g, src, dst, f, a, b, gw, zc, s);
-        case 2: return launch_tb<T, 2>(g, src, dst, f, a, b, gw, zc, s);
-        case 4: return launch_tb<T, 4>(g, src, dst, f, a, b, gw, zc, s);
-        case 8: return launch_tb<T, 8>(g, src, dst, f, a, b, gw, zc, s);
-        default: return hipErrorInvalidValue;
-    }
-}
-
-}  // namespace
+extern template struct JacobiLevels<1>;
+extern template struct JacobiLevels<2>;
+extern template struct JacobiLevels<3>;
+extern template struct JacobiLevels<4>;
+extern template struct JacobiLevels<5>;
+extern template struct JacobiLevels<6>;
+extern template struct JacobiLevels<7>;
+extern template struct JacobiLevels<8>;
 
 JacTileCfg jacobi_tile_cfg(bool fp32, int tb) {
-    if (fp32) {
-        switch (tb) {
-            case 1: return cfg_of<float, 1>();
-            case 2: return cfg_of<float, 2>();
-            case 4: return cfg_of<float, 4>();
-            default: return cfg_of<float, 8>();
-        }
-    }
     switch (tb) {
-        case 1: return cfg_of<double, 1>();
-        case 2: return cfg_of<double, 2>();
-        case 4: return cfg_of<double, 4>();
-        default: return cfg_of<double, 8>();
+        case 1: return JacobiLevels<1>::cfg(fp32);
+        case 2: return JacobiLevels<2>::cfg(fp32);
+        case 3: return JacobiLevels<3>::cfg(fp32);
+        case 4: return JacobiLevels<4>::cfg(fp32);
+        case 5: return JacobiLevels<5>::cfg(fp32);
+        case 6: return JacobiLevels<6>::cfg(fp32);
+        case 7: return JacobiLevels<7>::cfg(fp32);
+        default: return JacobiLevels<8>::cfg(fp32);
     }
 }
 
 hipError_t launch_jacobi_pass(bool fp32, int tb, const Geom &g, const void *src, void *dst,
                               const void *f, double a, double b, double gw, int zc,
                               hipStream_t s) {
-    return fp32 ? launch_any<float>(tb, g, src, dst, f, a, b, gw, zc, s)
-                : launch_any<double>(tb, g, src, dst, f, a, b, gw, zc, s);
+    switch (tb) {
+        case 1: return JacobiLevels<1>::pass(fp32, g, src, dst, f, a, b, gw, zc, s);
+        case 2: return JacobiLevels<2>::pass(fp32, g, src, dst, f, a, b, gw, zc, s);
+        case 3: return JacobiLevels<3>::pass(fp32, g, src, dst, f, a, b, gw, zc, s);
+        case 4: return JacobiLevels<4>::pass(fp32, g, src, dst, f, a, b, gw, zc, s);
+        case 5: return JacobiLevels<5>::pass(fp32, g, src, dst, f, a, b, gw, zc, s);
+        case 6: return JacobiLevels<6>::pass(fp32, g, src, dst, f, a, b, gw, zc, s);
+        case 7: return JacobiLevels<7>::pass(fp32, g, src, dst, f, a, b, gw, zc, s);
+        case 8: return JacobiLevels<8>::pass(fp32, g, src, dst, f, a, b, gw, zc, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
-size_t jacobi_batch_table_bytes(int njobs) {
-    return (size_t)njobs * (sizeof(JacJob<double>) > sizeof(JacJob<float>) ? sizeof(JacJob<double>)
-                                                                           : sizeof(JacJob<float>));
-}
+size_t jacobi_batch_table_bytes(int njobs) { return JacobiLevels<1>::table_bytes(njobs); }
 
 hipError_t launch_jacobi_batch(bool fp32, int tb, bool has_a, bool has_f,
                                const std::vector<JacBatchItem> &items, void *table_dev,
                                std::vector<unsigned char> &host_buf, hipStream_t s) {
     if (items.empty()) return hipSuccess;
-    return fp32 ? launch_batch_any<float>(tb, has_a, has_f, items, table_dev, host_buf, s)
-                : launch_batch_any<double>(tb, has_a, has_f, items, table_dev, host_buf, s);
+    switch (tb) {
+        case 1: return JacobiLevels<1>::batch(fp32, has_a, has_f, items, table_dev, host_buf, s);
+        case 2: return JacobiLevels<2>::batch(fp32, has_a, has_f, items, table_dev, host_buf, s);
+        case 3: return JacobiLevels<3>::batch(fp32, has_a, has_f, items, table_dev, host_buf, s);
+        case 4: return JacobiLevels<4>::batch(fp32, has_a, has_f, items, table_dev, host_buf, s);
+        case 5: return JacobiLevels<5>::batch(fp32, has_a, has_f, items, table_dev, host_buf, s);
+        case 6: return JacobiLevels<6>::batch(fp32, has_a, has_f, items, table_dev, host_buf, s);
+        case 7: return JacobiLevels<7>::batch(fp32, has_a, has_f, items, table_dev, host_buf, s);
+        case 8: return JacobiLevels<8>::batch(fp32, has_a, has_f, items, table_dev, host_buf, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace stk

@@ -1,0 +1,6 @@
+// Fused Jacobi pass with 2 time levels on chip (kernels in jacobi_impl.h).
+#include "jacobi_impl.h"
+
+namespace stk {
+template struct JacobiLevels<2>;
+}  // namespace stk

@@ -1,0 +1,6 @@
+// Fused Jacobi pass with 6 time levels on chip (kernels in jacobi_impl.h).
+#include "jacobi_impl.h"
+
+namespace stk {
+template struct JacobiLevels<6>;
+}  // namespace stk

@@ -422,7 +422,7 @@ int fail(int status, const std::string &m) {
 
 // Pass schedule shared with stencil_jacobi (api.cpp).
 namespace stk {
-std::vector<int> jacobi_pass_plan(bool fp32, int sweeps, int t_fuse, bool *final_copy);
+std::vector<int> jacobi_pass_plan(bool fp32, bool rhs, int sweeps, int t_fuse, bool *final_copy);
 }
 
 extern "C" {
@@ -503,7 +503,7 @@ int smooth_submit(smooth_ctx *c, const smooth_job *job, uint64_t *job_id) {
     j->st.lups = (double)job->nx * job->ny * job->nz * job->sweeps;
     if (!j->gs && job->sweeps > 0) {
         bool fc = false;
-        j->plan = jacobi_pass_plan(j->refined, job->sweeps, c->cfg.t_fuse, &fc);
+        j->plan = jacobi_pass_plan(j->refined, j->refined, job->sweeps, c->cfg.t_fuse, &fc);
     }
     std::lock_guard<std::mutex> lk(c->mu);
     if (c->stop) return fail(ST_EBUSY, "service is shutting down");

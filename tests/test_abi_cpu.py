@@ -53,7 +53,7 @@ FAKE2 = ctypes.c_void_p(0x90000000)
 
 @pytest.mark.parametrize("kw,status", [
     (dict(nx=0), -1), (dict(h=0), -1), (dict(dtype=7), -1), (dict(u=None), -1),
-    (dict(scratch=None), -1), (dict(t=3), -1), (dict(sweeps=-1), -1), (dict(bc=9), -1),
+    (dict(scratch=None), -1), (dict(t=9), -1), (dict(sweeps=-1), -1), (dict(bc=9), -1),
     (dict(overlap=True), -1), (dict(w=None), -1), (dict(nx=1 << 40), -1),
 ])
 def test_jacobi_validation(P, kw, status):
@@ -68,7 +68,7 @@ def test_jacobi_validation(P, kw, status):
     assert L.stencil_last_error()
 
 
-@pytest.mark.parametrize("kw", [dict(nz=0), dict(dtype=2), dict(u=None), dict(t=5),
+@pytest.mark.parametrize("kw", [dict(nz=0), dict(dtype=2), dict(u=None), dict(t=11),
                                 dict(sweeps=-3), dict(ny=9000)])
 def test_gs_validation(P, kw):
     L = P.lib()
@@ -84,7 +84,7 @@ def test_refine_and_residual_validation(P):
     g = _grid(P)
     od, rel = ctypes.c_int32(0), ctypes.c_double(0)
     args = dict(method=0, dt=1, u=FAKE, fp=FAKE2, m=4, t=0, tol=1e-10, mo=5)
-    for bad in (dict(method=2), dict(dt=3), dict(u=None), dict(fp=None), dict(m=0), dict(t=6),
+    for bad in (dict(method=2), dict(dt=3), dict(u=None), dict(fp=None), dict(m=0), dict(t=10),
                 dict(tol=-1.0), dict(mo=-1)):
         a = dict(args, **bad)
         rc = L.stencil_refine_solve(ctypes.byref(g), a["method"], a["dt"], a["u"], a["fp"], a["m"],
@@ -125,18 +125,29 @@ def test_strerror(P):
 def test_jacobi_plan(P, fp32):
     """Every schedule sums to the sweep count, uses only compiled depths, and
     leaves the result in u (even pass count) unless only 1-sweep passes exist."""
+    auto = max(P.jacobi_plan(40, 0, fp32=fp32)[0])
+    assert 1 <= auto <= 8
+    assert P.jacobi_plan(100, 0, fp32=fp32)[0] == [5] * 20
+    assert max(P.jacobi_plan(40, 0, fp32=fp32, rhs=True)[0]) == (6 if fp32 else 4)
     for S in list(range(0, 40)) + [64, 99, 100, 101, 255]:
-        for t in (0, 1, 2, 4, 8, 16):
+        for t in (0, 1, 2, 3, 4, 5, 6, 7, 8, 16):
             plan, fc = P.jacobi_plan(S, t, fp32=fp32)
             assert sum(plan) == S
-            tmax = {0: (8 if fp32 else 4), 16: 8}.get(t, t)
-            assert all(p in (1, 2, 4, 8) and p <= tmax for p in plan)
+            tmax = {0: auto, 16: 8}.get(t, t)
+            assert all(1 <= p <= tmax for p in plan)
             if fc:
                 assert len(plan) % 2 == 1 and all(p == 1 for p in plan)
             else:
                 assert len(plan) % 2 == 0
     plan, _ = P.jacobi_plan(100, 4)
     assert len(plan) == 26  # 25 passes of 4, odd: one of them split in two
+    plan, _ = P.jacobi_plan(100, 5)
+    assert plan == [5] * 20
+    plan, fc = P.jacobi_plan(13, 5)
+    assert sorted(plan) == [1, 2, 5, 5] and not fc  # 5+5+3, the 3 split as 2+1
+    for bad in (-1, 9, 12, 17):
+        with pytest.raises(Exception):
+            P.jacobi_plan(10, bad)
 
 
 def test_pool_allocator(tmp_path):

@@ -42,7 +42,7 @@ def _run_gs(P, u, sweeps, t=0, a=0.0, b=1.0 / 6.0, f=None, g=0.0, h=1):
 
 # --- the 64^3 workload: ghost 0, interior U[0,1), a=0, b=1/6, 10 sweeps -------
 
-@pytest.mark.parametrize("t", [1, 2, 4, 8, 16, 0])
+@pytest.mark.parametrize("t", [1, 2, 3, 4, 5, 6, 7, 8, 16, 0])
 def test_jacobi_64_all_t(P, olib, t):
     w = si.jacobi_small(seed=0)
     say("jacobi 64^3 x10 t=%d" % t)
@@ -73,7 +73,7 @@ def test_jacobi_ragged(P, olib, case, dtype):
     dt = np.float64 if dtype == "f64" else np.float32
     u = si.uniform_padded(nx, ny, nz, h, seed=nx + 7 * ny, lo=-1.0, hi=1.0).astype(dt)
     f = si.uniform_rhs(nx, ny, nz, seed=3).astype(dt)
-    for t in (1, 2, 4, 8):
+    for t in range(1, 9):
         for (a, b, g, ff) in ((0.0, 1.0 / 6.0, 0.0, None), (0.3, 0.1, 0.25, f),
                               (0.0, 1.0 / 6.0, 1.0 / 6.0, f)):
             say("jacobi", case, dtype, "t=%d a=%g rhs=%s" % (t, a, ff is not None))
@@ -102,7 +102,7 @@ def test_jacobi_split_invariance(P, olib):
 
 # --- full size: 512^3, 100 sweeps, sampled against the oracle -----------------
 
-@pytest.mark.parametrize("t", [4, 8])
+@pytest.mark.parametrize("t", [4, 5, 8])
 def test_jacobi_512_sampled(P, olib, t):
     w = si.jacobi_512(seed=0)
     u = w["u"]
