@@ -155,6 +155,65 @@ def cpu_baseline(n, target_s=15.0):
                       "C oracle, %.1f s" % (n, S, dt)}
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def cpu_threads_baseline(n, target_s=10.0):
+    """The oracle's Jacobi loops with the k loop on all OpenMP threads the
+    process may use (OMP_NUM_THREADS, else every core): a CPU Jacobi
+    baseline next to the single-threaded oracle."""
+    import oracle
+    import synthetic_inputs as si
+    lib = oracle.load()
+    u = si.jacobi_512(seed=0, n=n)["u"]
+    oracle.jacobi_threads(u, 1, lib=lib)
+    t0 = time.perf_counter()
+    oracle.jacobi_threads(u, 1, lib=lib)
+    t1 = time.perf_counter()
+    oracle.jacobi_threads(u, 3, lib=lib)
+    t3 = time.perf_counter()
+    one = max((t3 - t1) - (t1 - t0), 1e-3) / 2
+    S = max(1, min(100, int(round(target_s / one))))
+    t0 = time.perf_counter()
+    _, used = oracle.jacobi_threads(u, S, lib=lib)
+    dt = time.perf_counter() - t0
+    return {"value": round(float(n) ** 3 * S / dt / 1e6, 1), "unit": "MLUP/s", "cores": used,
+            "kind": "oracle loops, OpenMP over k",
+            "sample": "FP64 Jacobi %d^3 x %d sweeps, %d threads, %.1f s" % (n, S, used, dt)}
+
+
+def cpu_refine_oracle(ns=(32, 64), m=32, tol=1e-10):
+    """The oracle's defect-correction solve (FP64 throughout, and with float
+    inner sweeps) to rel <= tol on the Poisson workload at small n, single
+    thread: the CPU side of the solve comparison."""
+    import oracle
+    import synthetic_inputs as si
+    lib = oracle.load()
+    out = {}
+    for n in ns:
+        w = si.poisson(n=n, seed=0)
+        fp = w["f"] / float((n + 1) ** 2)
+        for method, name in ((0, "jacobi"), (1, "gauss_seidel")):
+            for inner_f32, key in ((True, "fp32_refined"), (False, "plain_fp64")):
+                t0 = time.perf_counter()
+                _, rc, outer, rel = oracle.refine(w["u"], fp, method=method, inner_f32=inner_f32,
+                                                  m=m, tol=tol, max_outer=10 ** 6, lib=lib)
+                dt = time.perf_counter() - t0
+                out["%d_%s_%s" % (n, name, key)] = {
+                    "seconds": round(dt, 3), "outer_rounds": outer, "sweeps": outer * m,
+                    "rel_residual": rel, "status": rc,
+                    "MLUPs": round(float(n) ** 3 * outer * m / dt / 1e6, 1)}
+                log("cpu oracle refine %d^3 %s %s: %s" % (n, name, key, out["%d_%s_%s" % (n, name, key)]))
+    return out
+
+
 def cpu_gs_oracle(n=384, sweeps=50):
     """The CPU oracle's lexicographic Gauss-Seidel (inherently sequential,
     single thread) on the full 384^3 x 50 workload."""
@@ -402,7 +461,12 @@ def main():
             u0.copy_(ug)
             m = events_time(torch, lambda: P.gauss_seidel(u0, g["sweeps"], t_fuse=t), reps=1)
             key = "all_sweeps_in_flight" if t == 0 else "one_launch_per_sweep"
-            gs[key] = {"ms": round(m, 3), "MLUPs": round(gl / (m * 1e-3) / 1e6)}
+            # algorithmic HBM bytes: one load and one store per site per launch
+            launches = 1 if t == 0 else g["sweeps"]
+            gbytes = 2 * 8 * 384.0 ** 3 * launches
+            gs[key] = {"ms": round(m, 3), "MLUPs": round(gl / (m * 1e-3) / 1e6),
+                       "hbm_bytes_algorithmic": gbytes,
+                       "hbm_frac": round(gbytes / (m * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
             log("gs 384^3 x50 %s: %s" % (key, gs[key]))
         extra["gs_384_x50"] = gs
         del ug, u0
@@ -415,6 +479,11 @@ def main():
         methods = tuple(names[x] for x in args.poisson_methods.split(","))
         extra["poisson_%d" % args.poisson_n] = poisson_compare(P, torch, args.poisson_n,
                                                                methods=methods, m=args.poisson_m)
+
+    if "poisson" in sections:
+        # the sizes the CPU oracle solves too (cpu_oracle_poisson_small)
+        for ns in (32, 64):
+            extra["poisson_%d" % ns] = poisson_compare(P, torch, ns, m=args.poisson_m)
     if "serving" in sections and args.serving_jobs > 0:
         rates = [float(x) for x in str(args.serving_rate).split(",")]
         runs = []
@@ -443,11 +512,15 @@ def main():
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(n)
-        line["cpu_baseline"]["host"] = platform.processor() or platform.machine()
+        line["cpu_baseline"]["host"] = cpu_model()
         line["cpu_baseline"]["host_threads_available"] = os.cpu_count()
+        extra["cpu_threads_baseline"] = cpu_threads_baseline(n)
+        log("cpu threads baseline: %s" % extra["cpu_threads_baseline"])
         if "gs" in sections:
             extra["cpu_oracle_gs_384_x50"] = cpu_gs_oracle()
             log("cpu oracle gs: %s" % extra["cpu_oracle_gs_384_x50"])
+        if "poisson" in sections:
+            extra["cpu_oracle_poisson_small"] = cpu_refine_oracle()
     line.update(extra)
     print(json.dumps(line), flush=True)
 

@@ -22,7 +22,7 @@ _HERE = pathlib.Path(__file__).resolve().parent
 _SRC = _HERE / "oracle.c"
 _LIB_PATH = _HERE / "liboracle.so"
 CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fno-unsafe-math-optimizations",
-          "-fPIC", "-shared", "-std=c11"]
+          "-fopenmp", "-fPIC", "-shared", "-std=c11"]
 
 _lib = None
 
@@ -55,6 +55,8 @@ def _bind(lib):
         fn = getattr(lib, name)
         fn.argtypes = [i64, i64, i64, i64, vp, vp, dbl, dbl, dbl, i32]
         fn.restype = i32
+    lib.oracle_jacobi_f64_threads.argtypes = [i64, i64, i64, i64, vp, dbl, dbl, i32, i32]
+    lib.oracle_jacobi_f64_threads.restype = i32
     lib.oracle_sumsq.argtypes = [vp, i64]
     lib.oracle_sumsq.restype = dbl
     lib.oracle_residual_f64.argtypes = [i64, i64, i64, i64, vp, vp, vp]
@@ -103,6 +105,19 @@ def gauss_seidel(u, sweeps, a=0.0, b=1.0 / 6.0, f=None, g=0.0, h=1, lib=None):
     """`sweeps` in-place lexicographic Gauss-Seidel sweeps."""
     kind = "gs_f32" if np.asarray(u).dtype == np.float32 else "gs_f64"
     return _smooth(kind, u, h, f, a, b, g, sweeps, lib)
+
+
+def jacobi_threads(u, sweeps, a=0.0, b=1.0 / 6.0, h=1, threads=0, lib=None):
+    """The FP64 Jacobi loops with the k loop on OpenMP threads (CPU baseline;
+    same result as `jacobi`).  Returns (result, threads used)."""
+    lib = lib or load()
+    out = np.ascontiguousarray(u, dtype=np.float64).copy()
+    nx, ny, nz = _dims(out, h)
+    used = lib.oracle_jacobi_f64_threads(nx, ny, nz, h, _ptr(out), float(a), float(b),
+                                         int(sweeps), int(threads))
+    if used < 1:
+        raise MemoryError("oracle allocation failed")
+    return out, used
 
 
 def smooth(method, u, sweeps, **kw):

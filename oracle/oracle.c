@@ -8,7 +8,8 @@
  * the GPU library (paper_1004_1741_amd/) and must never be used as a fallback
  * for it.
  *
- * Build: gcc -O2 -ffp-contract=off -fno-fast-math -shared -fPIC
+ * Build: gcc -O2 -ffp-contract=off -fno-fast-math -fopenmp -shared -fPIC
+ * (OpenMP is used only by oracle_jacobi_f64_threads, the CPU baseline)
  * (no FMA contraction, no reassociation, SSE2 doubles, round-to-nearest-even).
  *
  * Grid layout: interior extents nx, ny, nz and a ghost layer of width h >= 1;
@@ -38,6 +39,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define IDX(k, j, i) ((((int64_t)(k)) * py + (j)) * px + (i))
 #define FIDX(k, j, i) ((((int64_t)(k) - h) * ny + ((j) - h)) * nx + ((i) - h))
@@ -81,6 +85,51 @@ int oracle_jacobi_f64(int64_t nx, int64_t ny, int64_t nz, int64_t h, double *u,
         free(dst);
     }
     return 0;
+}
+
+/* CPU baseline: the Jacobi loop nest above without a right-hand side, its k
+ * loop split across OpenMP threads.  Every site sees the same operations in
+ * the same order, so the result equals oracle_jacobi_f64 for any thread
+ * count.  nthreads <= 0 means the OpenMP default.  Returns the number of
+ * threads used, or -2 if the second array cannot be allocated. */
+int oracle_jacobi_f64_threads(int64_t nx, int64_t ny, int64_t nz, int64_t h, double *u,
+                              double a, double b, int sweeps, int nthreads)
+{
+    const int64_t px = nx + 2 * h, py = ny + 2 * h, pz = nz + 2 * h;
+    const int64_t n = px * py * pz;
+    double *src = u;
+    double *dst = (double *)malloc((size_t)n * sizeof(double));
+    int used = 1;
+    if (!dst) return -2;
+    memcpy(dst, u, (size_t)n * sizeof(double));
+    for (int it = 0; it < sweeps; it++) {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) num_threads(nthreads > 0 ? nthreads : omp_get_max_threads())
+#endif
+        for (int64_t k = h; k < h + nz; k++) {
+#ifdef _OPENMP
+            if (k == h) used = omp_get_num_threads();
+#endif
+            for (int64_t j = h; j < h + ny; j++)
+                for (int64_t i = h; i < h + nx; i++) {
+                    double s = src[IDX(k, j, i - 1)];
+                    s = s + src[IDX(k, j, i + 1)];
+                    s = s + src[IDX(k, j - 1, i)];
+                    s = s + src[IDX(k, j + 1, i)];
+                    s = s + src[IDX(k - 1, j, i)];
+                    s = s + src[IDX(k + 1, j, i)];
+                    dst[IDX(k, j, i)] = (a != 0.0) ? (a * src[IDX(k, j, i)]) + (b * s) : b * s;
+                }
+        }
+        double *t = src; src = dst; dst = t;
+    }
+    if (src != u) {
+        memcpy(u, src, (size_t)n * sizeof(double));
+        free(src);
+    } else {
+        free(dst);
+    }
+    return used;
 }
 
 /* Lexicographic Gauss-Seidel, Sec. 3: `sweeps` in-place sweeps. */

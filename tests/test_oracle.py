@@ -51,3 +51,14 @@ def test_golden_fixture(lib):
     for case in golden_io.load_cases():
         out = golden_io.run_case(case, lib)
         assert np.array_equal(out, case["expected"]), case["name"]
+
+
+@pytest.mark.parametrize("threads", [1, 3, 8])
+def test_threaded_jacobi_baseline_matches(lib, threads):
+    """The OpenMP CPU baseline only splits the k loop: same bits as the
+    single-threaded loop nest for any thread count, weights and ghost width."""
+    for (a, b, h) in ((0.0, 1.0 / 6.0, 1), (0.3, 0.1, 2)):
+        u = si.uniform_padded(23, 19, 11, h, seed=threads, lo=-1.0, hi=1.0)
+        got, used = oracle.jacobi_threads(u, 5, a=a, b=b, h=h, threads=threads, lib=lib)
+        assert 1 <= used <= threads
+        assert np.array_equal(got, oracle.jacobi(u, 5, a=a, b=b, h=h, lib=lib))
