@@ -18,7 +18,11 @@
 //     yet overwritten by (jj+1,kk)/(jj,kk+1);
 //   * the bundle's lines and the four neighbour lines around it are staged in
 //     an LDS ring of 32 x positions, loaded and stored in coalesced chunks of
-//     8 positions;
+//     8 positions.  Chunk boundaries follow each line's own alignment (chunk c
+//     of a line covers positions [8c - s, 8c + 8 - s), s = the element offset
+//     of position 0 past an 8-element boundary), so a chunk is one aligned
+//     64-byte (FP64) or 32-byte (FP32) segment instead of straddling two:
+//     partial-segment writes cost 1.5x the stored bytes at the memory side;
 //   * items (tau, J, K) are handed out by an atomic ticket in order of
 //     2*tau + J + K, a topological order of their dependencies, so a wave only
 //     ever waits on items already held by running waves (no deadlock, no
@@ -56,8 +60,8 @@ struct GsJob {
     int nx, ny, nz, h;
     T a, b, g;
     int nj, nk;          // bundles in y and z
-    int ncs;             // store chunks per line
-    int ncl;             // load chunks per line (includes the x+ ghost)
+    int ncs;             // store chunks per line (positions < nx for any shift)
+    int ncl;             // load chunks per line (up to the x+ ghost, any shift)
     int nb;              // step blocks
     uint32_t *progress;  // [sweep][bundle]: chunks stored so far
 };
@@ -135,9 +139,13 @@ __device__ __forceinline__ void gs_item(const GsJob<T> &A, int tau, int J, int K
 
         // Per-item staging tables: lane-constant line pointers and LDS offsets
         // of the 12 (load) and 8 (store) elements this lane moves per chunk.
+        // Element m of a chunk is position 8c + xoff - lsh[m] of its line, where
+        // lsh is that line's shift (the same for every item touching the line,
+        // so producers and consumers agree on what "chunk c" holds).
         const T *lsrc[12];
         int lring[12];
         bool lok[12];
+        int lsh[12];
 #pragma unroll
         for (int m = 0; m < 12; ++m) {
             const int e = lane + 64 * m;
@@ -145,12 +153,15 @@ __device__ __forceinline__ void gs_item(const GsJob<T> &A, int tau, int J, int K
             const int jl = slot % 10, kl = slot / 10;
             const int jg = j0 - 1 + jl, kg = k0 - 1 + kl;
             lok[m] = jg <= h + A.ny && kg <= h + A.nz;
-            lsrc[m] = A.u + (int64_t)kg * A.plane + (int64_t)jg * A.px + h + (e & 7);
+            const T *l0 = A.u + (int64_t)kg * A.plane + (int64_t)jg * A.px + h;
+            lsh[m] = (int)((reinterpret_cast<uintptr_t>(l0) / sizeof(T)) & (GS_C - 1));
+            lsrc[m] = l0 + (e & 7) - lsh[m];
             lring[m] = slot * GS_S;
         }
         T *sdst[8];
         int sring[8];
         bool sok[8];
+        int ssh[8];
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
             const int e = lane + 64 * m;
@@ -158,10 +169,12 @@ __device__ __forceinline__ void gs_item(const GsJob<T> &A, int tau, int J, int K
             const int jq = li & 7, kq = li >> 3;
             const int jg = j0 + jq, kg = k0 + kq;
             sok[m] = jg < h + A.ny && kg < h + A.nz;
-            sdst[m] = A.u + (int64_t)kg * A.plane + (int64_t)jg * A.px + h + (e & 7);
+            T *l0 = A.u + (int64_t)kg * A.plane + (int64_t)jg * A.px + h;
+            ssh[m] = (int)((reinterpret_cast<uintptr_t>(l0) / sizeof(T)) & (GS_C - 1));
+            sdst[m] = l0 + (e & 7) - ssh[m];
             sring[m] = ((kq + 1) * 10 + (jq + 1)) * GS_S;
         }
-        const int xoff = lane & 7;  // position within a chunk of every element
+        const int xoff = lane & 7;  // chunk-relative position of every element
 
         // Dependencies: own bundle at tau-1, (J+1,K) and (J,K+1) at tau-1 (old
         // values), (J-1,K) and (J,K-1) at tau (fresh values).  The five polls
@@ -173,7 +186,7 @@ __device__ __forceinline__ void gs_item(const GsJob<T> &A, int tau, int J, int K
         const bool has[5] = {tau > 0, tau > 0 && J + 1 < A.nj, tau > 0 && K + 1 < A.nk, J > 0,
                              K > 0};
         auto wait_chunk = [&](int c) {
-            if (c * GS_C >= A.nx) return;  // only the x+ ghost column: never written
+            if (c >= A.ncs) return;  // only positions >= nx: never written
             const uint32_t need = (uint32_t)c + 1u;
             uint32_t v[5];
 #pragma unroll
@@ -197,11 +210,14 @@ __device__ __forceinline__ void gs_item(const GsJob<T> &A, int tau, int J, int K
         T pf[12];  // chunk in flight from global memory
         T fpf[HAS_F ? 8 : 1];
         auto issue_load = [&](int c) {
-            const int i = c * GS_C + xoff;
-            const bool iok = i <= A.nx;
+            const int q = c * GS_C + xoff;
 #pragma unroll
-            for (int m = 0; m < 12; ++m)
-                pf[m] = (iok && lok[m]) ? coherent_load(lsrc[m] + c * GS_C) : T(0);
+            for (int m = 0; m < 12; ++m) {
+                const int i = q - lsh[m];  // 0..nx: interior and the x+ ghost
+                pf[m] = (lok[m] && (unsigned)i <= (unsigned)A.nx)
+                            ? coherent_load(lsrc[m] + c * GS_C)
+                            : T(0);
+            }
             if constexpr (HAS_F) {
 #pragma unroll
                 for (int m = 0; m < 8; ++m) {
@@ -209,35 +225,35 @@ __device__ __forceinline__ void gs_item(const GsJob<T> &A, int tau, int J, int K
                     const int li = e >> 3;
                     const int jq = li & 7, kq = li >> 3;
                     const int jg = j0 + jq, kg = k0 + kq;
-                    fpf[m] = (i < A.nx && sok[m])
+                    const int i = q - ssh[m];  // f follows its u line's chunking
+                    fpf[m] = ((unsigned)i < (unsigned)A.nx && sok[m])
                                  ? A.f[((int64_t)(kg - h) * A.ny + (jg - h)) * A.nx + i]
                                  : T(0);
                 }
             }
         };
         auto commit_load = [&](int c) {  // prefetched chunk -> LDS ring
-            const int r = (c * GS_C + xoff) & (GS_RING - 1);
+            const int q = c * GS_C + xoff;
 #pragma unroll
-            for (int m = 0; m < 12; ++m) ring[lring[m] + r] = pf[m];
+            for (int m = 0; m < 12; ++m) ring[lring[m] + ((q - lsh[m]) & (GS_RING - 1))] = pf[m];
             if constexpr (HAS_F) {
 #pragma unroll
                 for (int m = 0; m < 8; ++m) {
                     const int li = (lane + 64 * m) >> 3;
-                    fring[((li >> 3) * 10 + (li & 7)) * GS_S + r] = fpf[m];
+                    fring[((li >> 3) * 10 + (li & 7)) * GS_S + ((q - ssh[m]) & (GS_RING - 1))] =
+                        fpf[m];
                 }
             }
         };
         auto issue_store = [&](int c) {  // LDS ring -> global (not yet published)
-            const int i = c * GS_C + xoff;
-            const int r = i & (GS_RING - 1);
+            const int q = c * GS_C + xoff;
             T v[8];
 #pragma unroll
-            for (int m = 0; m < 8; ++m) v[m] = ring[sring[m] + r];
-            if (i < A.nx) {
+            for (int m = 0; m < 8; ++m) v[m] = ring[sring[m] + ((q - ssh[m]) & (GS_RING - 1))];
 #pragma unroll
-                for (int m = 0; m < 8; ++m)
-                    if (sok[m]) coherent_store(sdst[m] + c * GS_C, v[m]);
-            }
+            for (int m = 0; m < 8; ++m)
+                if (sok[m] && (unsigned)(q - ssh[m]) < (unsigned)A.nx)
+                    coherent_store(sdst[m] + c * GS_C, v[m]);
         };
         auto publish = [&](int c) {  // stores of chunk c have completed
             if (lane == 0)
@@ -431,8 +447,9 @@ GsJob<T> make_job(const Geom &g, void *u, const void *f, double a, double b, dou
     A.a = (T)a; A.b = (T)b; A.g = (T)gw;
     A.nj = (g.ny + 7) / 8;
     A.nk = (g.nz + 7) / 8;
-    A.ncs = (g.nx + GS_C - 1) / GS_C;
-    A.ncl = (g.nx + 1 + GS_C - 1) / GS_C;
+    // with line shifts 0..7: stores reach position nx-1, loads the x+ ghost nx
+    A.ncs = (g.nx + GS_C - 2) / GS_C + 1;
+    A.ncl = (g.nx + GS_C - 1) / GS_C + 1;
     A.nb = (g.nx + 14 + GS_C - 1) / GS_C;
     A.progress = progress;
     return A;

@@ -8,6 +8,12 @@ checks the protocol itself (termination for any interleaving and the
 fresh/old data each site reads), independently of the HIP code.  Values are
 computed with the Sec. 3 update in the same operand order, so the result must
 equal the oracle's sequential sweep bit for bit.
+
+Chunks are aligned per line: chunk c of a line covers positions
+[8c - s, 8c + 8 - s), where s (0..7) is the line's element offset of i = 0
+from an 8-element boundary of the array (base_off shifts the whole array, as
+a different allocation alignment would).  Producer and consumer compute s
+from the same address, so "chunk c" names the same positions on both sides.
 """
 import random
 
@@ -35,7 +41,8 @@ def staged_slot(li):
     if li < 88: return 10 + (li - 8)
     return 90 + (li - 88) + 1
 
-def simulate(u0, S, h=1, workers=3, seed=0, a=0.0, b=1/6, p_early=0.3, publish_lag=3):
+def simulate(u0, S, h=1, workers=3, seed=0, a=0.0, b=1/6, p_early=0.3, publish_lag=3,
+             base_off=0, store_shift_error=0):
     """Run the schedule with `workers` interleaved waves.  Every global load
     and store takes effect at a random moment between its issue and the next
     point where the kernel waits for all of its memory operations (a chunk
@@ -46,7 +53,12 @@ def simulate(u0, S, h=1, workers=3, seed=0, a=0.0, b=1/6, p_early=0.3, publish_l
     pz, py, px = u.shape
     nz, ny, nx = pz-2*h, py-2*h, px-2*h
     nj, nk = (ny+7)//8, (nz+7)//8
-    ncs = (nx + C - 1)//C; ncl = (nx + 1 + C - 1)//C; nb = (nx + 14 + C - 1)//C
+    # chunk counts valid for every line shift s in 0..7: stores reach i = nx-1,
+    # loads the x+ ghost i = nx, blocks the last site of the most skewed lane
+    ncs = (nx + 6)//C + 1; ncl = (nx + 7)//C + 1; nb = (nx + 14 + C - 1)//C
+
+    def shift(kg, jg):  # element offset of (kg, jg, i=0) past an 8-element boundary
+        return (base_off + (kg*py + jg)*px + h) % C
     items = items_table(nj, nk, S)
     # topological check
     pos = {it: n for n, it in enumerate(items)}
@@ -80,7 +92,7 @@ def simulate(u0, S, h=1, workers=3, seed=0, a=0.0, b=1/6, p_early=0.3, publish_l
                 while pending:
                     pending.pop(0)()
             def wait_chunk(c):
-                if c*C >= nx: return
+                if c >= ncs: return  # only positions >= nx: never written
                 conds = []
                 if tau > 0:
                     conds.append((tau-1, me))
@@ -96,10 +108,11 @@ def simulate(u0, S, h=1, workers=3, seed=0, a=0.0, b=1/6, p_early=0.3, publish_l
                 vals = {}
                 def read():
                     for e in range(768):
-                        li = e >> 3; i = c*C + (e & 7)
+                        li = e >> 3
                         slot = staged_slot(li); jl, kl = slot % 10, slot // 10
                         jg, kg = j0-1+jl, k0-1+kl
-                        ok = i <= nx and jg <= h+ny and kg <= h+nz
+                        i = c*C + (e & 7) - shift(kg, jg)
+                        ok = 0 <= i <= nx and jg <= h+ny and kg <= h+nz
                         vals[e] = (slot, i & (RING-1), u[kg, jg, h+i] if ok else 0.0)
                 pf["c"] = (vals, read)
                 pending.append(read)
@@ -112,9 +125,10 @@ def simulate(u0, S, h=1, workers=3, seed=0, a=0.0, b=1/6, p_early=0.3, publish_l
             def issue_store(c):  # LDS read now; global write at some later moment
                 vals = []
                 for e in range(512):
-                    li = e >> 3; i = c*C + (e & 7); jq, kq = li & 7, li >> 3
+                    li = e >> 3; jq, kq = li & 7, li >> 3
                     jg, kg = j0+jq, k0+kq
-                    if i < nx and jg < h+ny and kg < h+nz:
+                    i = c*C + (e & 7) - (shift(kg, jg) + store_shift_error) % C
+                    if 0 <= i < nx and jg < h+ny and kg < h+nz:
                         vals.append((kg, jg, h+i, ring[(kq+1)*10 + jq+1, i & (RING-1)]))
                 def write():
                     for kg, jg, ig, v in vals:

@@ -18,6 +18,15 @@ def test_protocol_matches_sequential_sweeps(dims, S, workers, seed):
     assert np.array_equal(got, oracle.gauss_seidel(u0, S))
 
 
+@pytest.mark.parametrize("base_off", [1, 3, 6])
+def test_protocol_with_other_alignments(base_off):
+    """Chunk boundaries follow each line's own alignment; any array base
+    offset gives the sequential result."""
+    u0 = si.uniform_padded(37, 17, 12, 1, seed=base_off, lo=-1.0, hi=1.0)
+    got = M.simulate(u0, 3, workers=5, seed=base_off, base_off=base_off)
+    assert np.array_equal(got, oracle.gauss_seidel(u0, 3))
+
+
 def test_ticket_order_is_topological():
     items = M.items_table(5, 4, 6)
     pos = {it: n for n, it in enumerate(items)}
@@ -35,3 +44,11 @@ def test_protocol_model_catches_early_publish():
     u0 = si.uniform_padded(100, 30, 9, 1, seed=2, lo=-1.0, hi=1.0)
     got = M.simulate(u0, 5, workers=16, seed=2, publish_lag=2)
     assert not np.array_equal(got, oracle.gauss_seidel(u0, 5))
+
+
+def test_protocol_model_catches_misaligned_chunks():
+    """A store side whose chunk boundaries differ from the load side's (by one
+    element) publishes positions it has not stored; the model must see that."""
+    u0 = si.uniform_padded(37, 17, 12, 1, seed=4, lo=-1.0, hi=1.0)
+    got = M.simulate(u0, 3, workers=5, seed=4, base_off=2, store_shift_error=1)
+    assert not np.array_equal(got, oracle.gauss_seidel(u0, 3))
