@@ -174,6 +174,18 @@ __device__ __forceinline__ void gs_item(const GsJob<T> &A, int tau, int J, int K
             sdst[m] = l0 + (e & 7) - ssh[m];
             sring[m] = ((kq + 1) * 10 + (jq + 1)) * GS_S;
         }
+        // f (interior-only, its own row pitch) is staged with its own line
+        // alignment: f chunk c covers [8c - fsh, 8c + 8 - fsh) of the line.
+        int fsh[HAS_F ? 8 : 1];
+        if constexpr (HAS_F) {
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                const int li = (lane + 64 * m) >> 3;
+                const int jg = j0 + (li & 7), kg = k0 + (li >> 3);
+                const T *f0 = A.f + ((int64_t)(kg - h) * A.ny + (jg - h)) * A.nx;
+                fsh[m] = (int)((reinterpret_cast<uintptr_t>(f0) / sizeof(T)) & (GS_C - 1));
+            }
+        }
         const int xoff = lane & 7;  // chunk-relative position of every element
 
         // Dependencies: own bundle at tau-1, (J+1,K) and (J,K+1) at tau-1 (old
@@ -225,7 +237,7 @@ __device__ __forceinline__ void gs_item(const GsJob<T> &A, int tau, int J, int K
                     const int li = e >> 3;
                     const int jq = li & 7, kq = li >> 3;
                     const int jg = j0 + jq, kg = k0 + kq;
-                    const int i = q - ssh[m];  // f follows its u line's chunking
+                    const int i = q - fsh[m];
                     fpf[m] = ((unsigned)i < (unsigned)A.nx && sok[m])
                                  ? A.f[((int64_t)(kg - h) * A.ny + (jg - h)) * A.nx + i]
                                  : T(0);
@@ -240,7 +252,7 @@ __device__ __forceinline__ void gs_item(const GsJob<T> &A, int tau, int J, int K
 #pragma unroll
                 for (int m = 0; m < 8; ++m) {
                     const int li = (lane + 64 * m) >> 3;
-                    fring[((li >> 3) * 10 + (li & 7)) * GS_S + ((q - ssh[m]) & (GS_RING - 1))] =
+                    fring[((li >> 3) * 10 + (li & 7)) * GS_S + ((q - fsh[m]) & (GS_RING - 1))] =
                         fpf[m];
                 }
             }
