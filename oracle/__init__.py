@@ -51,7 +51,8 @@ def load(path: pathlib.Path | None = None):
 
 def _bind(lib):
     i64, i32, dbl, vp = ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_void_p
-    for name in ("oracle_jacobi_f64", "oracle_gs_f64", "oracle_jacobi_f32", "oracle_gs_f32"):
+    for name in ("oracle_jacobi_f64", "oracle_gs_f64", "oracle_jacobi_f32", "oracle_gs_f32",
+                 "oracle_rbgs_f64", "oracle_rbgs_f32"):
         fn = getattr(lib, name)
         fn.argtypes = [i64, i64, i64, i64, vp, vp, dbl, dbl, dbl, i32]
         fn.restype = i32
@@ -120,8 +121,14 @@ def jacobi_threads(u, sweeps, a=0.0, b=1.0 / 6.0, h=1, threads=0, lib=None):
     return out, used
 
 
+def red_black(u, sweeps, a=0.0, b=1.0 / 6.0, f=None, g=0.0, h=1, lib=None):
+    """`sweeps` in-place red-black Gauss-Seidel sweeps (red: i + j + k even)."""
+    kind = "rbgs_f32" if np.asarray(u).dtype == np.float32 else "rbgs_f64"
+    return _smooth(kind, u, h, f, a, b, g, sweeps, lib)
+
+
 def smooth(method, u, sweeps, **kw):
-    return (jacobi if method == 0 else gauss_seidel)(u, sweeps, **kw)
+    return (jacobi, gauss_seidel, red_black)[method](u, sweeps, **kw)
 
 
 def residual(u, fp, h=1, lib=None):

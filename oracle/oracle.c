@@ -30,6 +30,9 @@
  * fastest, then j, then k, all increasing), so x-, y-, z- are already new and
  * x+, y+, z+ are still old.
  *
+ * Red-black Gauss-Seidel (the common alternative ordering the paper names
+ * next to the lexicographic one) colours sites by the parity of i + j + k.
+ *
  * parity pins: tests/test_oracle.py (closed-form Jacobi decay of discrete sine
  * modes, harmonic fixed points, exact rational arithmetic with dyadic weights,
  * brute-force loop transcriptions, split invariance, defect-correction
@@ -159,6 +162,38 @@ int oracle_gs_f64(int64_t nx, int64_t ny, int64_t nz, int64_t h, double *u,
     return 0;
 }
 
+/* Red-black Gauss-Seidel: one sweep updates, in place, first every "red"
+ * site ((i + j + k) even, interior coordinates counted from 0) and then every
+ * "black" site, each with the same update as above.  Axis neighbours always
+ * have the other colour, so red sites read only old black values and black
+ * sites read the new red ones; the loop order within a colour is free. */
+int oracle_rbgs_f64(int64_t nx, int64_t ny, int64_t nz, int64_t h, double *u,
+                    const double *f, double a, double b, double g, int sweeps)
+{
+    const int64_t px = nx + 2 * h, py = ny + 2 * h;
+    for (int it = 0; it < sweeps; it++)
+        for (int color = 0; color < 2; color++)
+            for (int64_t k = h; k < h + nz; k++)
+                for (int64_t j = h; j < h + ny; j++)
+                    for (int64_t i = h; i < h + nx; i++) {
+                        if ((((i - h) + (j - h) + (k - h)) & 1) != color) continue;
+                        double s = u[IDX(k, j, i - 1)];
+                        s = s + u[IDX(k, j, i + 1)];
+                        s = s + u[IDX(k, j - 1, i)];
+                        s = s + u[IDX(k, j + 1, i)];
+                        s = s + u[IDX(k - 1, j, i)];
+                        s = s + u[IDX(k + 1, j, i)];
+                        double v;
+                        if (a != 0.0)
+                            v = (a * u[IDX(k, j, i)]) + (b * s);
+                        else
+                            v = b * s;
+                        if (f) v = v + (g * f[FIDX(k, j, i)]);
+                        u[IDX(k, j, i)] = v;
+                    }
+    return 0;
+}
+
 /* ---------------------------------------------------------------- FP32 ---- */
 /* Same loops with float storage and float arithmetic; weights are rounded to
  * float once (round-to-nearest-even). */
@@ -226,6 +261,35 @@ int oracle_gs_f32(int64_t nx, int64_t ny, int64_t nz, int64_t h, float *u,
                     u[IDX(k, j, i)] = v;
                 }
     }
+    return 0;
+}
+
+/* Red-black Gauss-Seidel in float (see oracle_rbgs_f64). */
+int oracle_rbgs_f32(int64_t nx, int64_t ny, int64_t nz, int64_t h, float *u,
+                    const float *f, double a64, double b64, double g64, int sweeps)
+{
+    const float a = (float)a64, b = (float)b64, g = (float)g64;
+    const int64_t px = nx + 2 * h, py = ny + 2 * h;
+    for (int it = 0; it < sweeps; it++)
+        for (int color = 0; color < 2; color++)
+            for (int64_t k = h; k < h + nz; k++)
+                for (int64_t j = h; j < h + ny; j++)
+                    for (int64_t i = h; i < h + nx; i++) {
+                        if ((((i - h) + (j - h) + (k - h)) & 1) != color) continue;
+                        float s = u[IDX(k, j, i - 1)];
+                        s = s + u[IDX(k, j, i + 1)];
+                        s = s + u[IDX(k, j - 1, i)];
+                        s = s + u[IDX(k, j + 1, i)];
+                        s = s + u[IDX(k - 1, j, i)];
+                        s = s + u[IDX(k + 1, j, i)];
+                        float v;
+                        if (a != 0.0f)
+                            v = (a * u[IDX(k, j, i)]) + (b * s);
+                        else
+                            v = b * s;
+                        if (f) v = v + (g * f[FIDX(k, j, i)]);
+                        u[IDX(k, j, i)] = v;
+                    }
     return 0;
 }
 

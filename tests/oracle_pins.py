@@ -18,7 +18,11 @@ Sources of truth used here (none re-types the oracle's own loops in FP):
     where every FP64 intermediate is exact;
   * Young's theorem: lexicographic Gauss-Seidel on the 7-point Laplacian
     (a consistently ordered matrix) converges asymptotically with the square
-    of the Jacobi rate, cos(pi/(n+1))^2;
+    of the Jacobi rate, cos(pi/(n+1))^2; the red-black ordering is
+    consistently ordered too, so red-black Gauss-Seidel has the same rate;
+  * red-black Gauss-Seidel written as two masked Jacobi half-sweeps with
+    numpy slicing (red sites from old values, then black sites from the new
+    red ones), independent of the oracle's loop nest;
   * defect correction: m sweeps on A e = r from e = 0 added to u0 equal m
     sweeps on u from u0 (linearity).
 """
@@ -85,35 +89,41 @@ def pin_fixed_points(lib):
         for a, b in ((0.25, 0.125), (0.5, 1.0 / 12.0 * 1.0)):
             if a + 6 * b != 1.0:
                 continue
-            for fn in (oracle.jacobi, oracle.gauss_seidel):
+            for fn in (oracle.jacobi, oracle.gauss_seidel, oracle.red_black):
                 out = fn(u, 6, a=a, b=b, lib=lib)
                 assert np.array_equal(out, u), (fn.__name__, a, b)
                 out32 = fn(u.astype(np.float32), 6, a=a, b=b, lib=lib)
                 assert np.array_equal(out32, u.astype(np.float32)), (fn.__name__, "f32")
     # b = 1/6 is not dyadic: at most a couple of ulps per sweep.
     u = np.full((nz + 2, ny + 2, nx + 2), 0.7)
-    for fn in (oracle.jacobi, oracle.gauss_seidel):
+    for fn in (oracle.jacobi, oracle.gauss_seidel, oracle.red_black):
         out = fn(u, 10, a=0.0, b=1.0 / 6.0, lib=lib)
         assert np.abs(out - 0.7).max() <= 10 * 2 * EPS64, fn.__name__
 
 
-def _frac_sweeps(u, f, a, b, g, sweeps, in_place):
-    """Sec. 3 definitions in exact rational arithmetic (order-free)."""
+def _frac_sweeps(u, f, a, b, g, sweeps, in_place, colors=None):
+    """Sec. 3 definitions in exact rational arithmetic (order-free).  With
+    colors=(0, 1) each sweep is two in-place passes over the sites whose
+    (i + j + k) parity (interior coordinates from 0) is that colour."""
     nz, ny, nx = len(u) - 2, len(u[0]) - 2, len(u[0][0]) - 2
     cur = [[[Fraction(v) for v in row] for row in plane] for plane in u]
+    passes = [(None, in_place)] if colors is None else [(c, True) for c in colors]
     for _ in range(sweeps):
-        src = cur
-        dst = cur if in_place else [[[v for v in row] for row in plane] for plane in cur]
-        for k in range(1, nz + 1):
-            for j in range(1, ny + 1):
-                for i in range(1, nx + 1):
-                    s = (src[k][j][i - 1] + src[k][j][i + 1] + src[k][j - 1][i]
-                         + src[k][j + 1][i] + src[k - 1][j][i] + src[k + 1][j][i])
-                    v = a * src[k][j][i] + b * s
-                    if f is not None:
-                        v += g * Fraction(f[k - 1][j - 1][i - 1])
-                    dst[k][j][i] = v
-        cur = dst
+        for color, inp in passes:
+            src = cur
+            dst = cur if inp else [[[v for v in row] for row in plane] for plane in cur]
+            for k in range(1, nz + 1):
+                for j in range(1, ny + 1):
+                    for i in range(1, nx + 1):
+                        if color is not None and (i + j + k - 3) % 2 != color:
+                            continue
+                        s = (src[k][j][i - 1] + src[k][j][i + 1] + src[k][j - 1][i]
+                             + src[k][j + 1][i] + src[k - 1][j][i] + src[k + 1][j][i])
+                        v = a * src[k][j][i] + b * s
+                        if f is not None:
+                            v += g * Fraction(f[k - 1][j - 1][i - 1])
+                        dst[k][j][i] = v
+            cur = dst
     return cur
 
 
@@ -138,8 +148,9 @@ def pin_exact_rational(lib):
                            (Fraction(0), Fraction(1, 8), Fraction(1, 2), True),
                            (Fraction(-1, 2), Fraction(1, 4), Fraction(3, 4), True)):
         ff = f if use_f else None
-        for in_place, fn in ((False, oracle.jacobi), (True, oracle.gauss_seidel)):
-            exact = _frac_sweeps(ul, fl if use_f else None, a, b, g, 5, in_place)
+        for in_place, fn, colors in ((False, oracle.jacobi, None), (True, oracle.gauss_seidel, None),
+                                     (True, oracle.red_black, (0, 1))):
+            exact = _frac_sweeps(ul, fl if use_f else None, a, b, g, 5, in_place, colors)
             out = fn(u, 5, a=float(a), b=float(b), f=ff, g=float(g), lib=lib)
             _check_frac(out, exact)
 
@@ -150,11 +161,13 @@ def pin_exact_rational_f32(lib):
     a, b, g = Fraction(1, 4), Fraction(1, 8), Fraction(1, 2)
     # Gauss-Seidel chains fresh values within a sweep, so its denominators grow
     # with the grid diagonal: keep its grid and sweep count smaller.
-    for in_place, fn, (nx, ny, nz), S in ((False, oracle.jacobi, (3, 4, 3), 3),
-                                          (True, oracle.gauss_seidel, (3, 2, 2), 1)):
+    for in_place, fn, (nx, ny, nz), S, colors in (
+            (False, oracle.jacobi, (3, 4, 3), 3, None),
+            (True, oracle.gauss_seidel, (3, 2, 2), 1, None),
+            (True, oracle.red_black, (3, 3, 2), 2, (0, 1))):
         u = rng.integers(-4, 5, size=(nz + 2, ny + 2, nx + 2)).astype(np.float64)
         f = rng.integers(-2, 3, size=(nz, ny, nx)).astype(np.float64)
-        exact = _frac_sweeps(u.tolist(), f.tolist(), a, b, g, S, in_place)
+        exact = _frac_sweeps(u.tolist(), f.tolist(), a, b, g, S, in_place, colors)
         out = fn(u.astype(np.float32), S, a=0.25, b=0.125, f=f.astype(np.float32), g=0.5, lib=lib)
         _check_frac(out.astype(np.float64), exact, mant_bits=24)
 
@@ -168,8 +181,9 @@ def pin_gs_rate(lib):
     u = np.zeros((n + 2, n + 2, n + 2))
     u[1:-1, 1:-1, 1:-1] = rng.random((n, n, n))
     rho_j = math.cos(math.pi / (n + 1))
-    for fn, expect in ((oracle.gauss_seidel, rho_j ** 2), (oracle.jacobi, rho_j)):
-        v = fn(u, 150 if fn is oracle.gauss_seidel else 300, lib=lib)
+    for fn, expect in ((oracle.gauss_seidel, rho_j ** 2), (oracle.red_black, rho_j ** 2),
+                       (oracle.jacobi, rho_j)):
+        v = fn(u, 300 if fn is oracle.jacobi else 150, lib=lib)
         w = fn(v, 1, lib=lib)
         ratio = np.linalg.norm(w) / np.linalg.norm(v)
         assert abs(ratio - expect) < 2e-3, (fn.__name__, ratio, expect)
@@ -321,6 +335,37 @@ def pin_listing_order(lib):
                           _listing_jacobi(u, 2, 0.3, 0.1))
 
 
+def pin_red_black_masks(lib):
+    """Red-black = masked Jacobi on the red sites, then on the black sites with
+    the new red values (numpy slicing, same operand order: bit-exact), and it
+    differs from the lexicographic sweep."""
+    rng = np.random.default_rng(5)
+    for h, (nx, ny, nz), a, b, use_f in ((1, (9, 6, 7), 0.0, 1.0 / 6.0, False),
+                                         (2, (5, 8, 4), 0.3, 0.11, True)):
+        u = rng.random((nz + 2 * h, ny + 2 * h, nx + 2 * h)) * 2 - 1
+        f = rng.random((nz, ny, nx)) - 0.5 if use_f else None
+        g = 0.25
+        kk, jj, ii = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+        parity = (ii + jj + kk) % 2
+        ref = u.copy()
+        I = (slice(h, h + nz), slice(h, h + ny), slice(h, h + nx))
+        for _ in range(3):
+            for color in (0, 1):
+                c = ref[I]
+                s = ref[h:h + nz, h:h + ny, h - 1:h + nx - 1] + ref[h:h + nz, h:h + ny, h + 1:h + nx + 1]
+                s = s + ref[h:h + nz, h - 1:h + ny - 1, h:h + nx]
+                s = s + ref[h:h + nz, h + 1:h + ny + 1, h:h + nx]
+                s = s + ref[h - 1:h + nz - 1, h:h + ny, h:h + nx]
+                s = s + ref[h + 1:h + nz + 1, h:h + ny, h:h + nx]
+                v = (a * c) + (b * s) if a != 0.0 else b * s
+                if f is not None:
+                    v = v + (g * f)
+                ref[I] = np.where(parity == color, v, c)
+        out = oracle.red_black(u, 3, a=a, b=b, f=f, g=g, h=h, lib=lib)
+        assert np.array_equal(out, ref), (h, a)
+        assert not np.array_equal(out, oracle.gauss_seidel(u, 3, a=a, b=b, f=f, g=g, h=h, lib=lib))
+
+
 ALL_PINS = [pin_listing_order, pin_jacobi_sine_decay, pin_fixed_points, pin_exact_rational, pin_exact_rational_f32,
             pin_gs_rate, pin_gs_differs_from_jacobi, pin_residual_mode, pin_defect_correction,
-            pin_manufactured_solution, pin_split_invariance]
+            pin_manufactured_solution, pin_split_invariance, pin_red_black_masks]

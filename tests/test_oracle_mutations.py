@@ -38,6 +38,12 @@ MUTATIONS = [
      "s = s + src[IDX(k, j + 1, i)];", "s = s + src[IDX(k + 1, j, i)];"),
     ("gs_f32_center_weight_dropped", "oracle_gs_f32",
      "v = (a * u[IDX(k, j, i)]) + (b * s);", "v = (b * s);"),
+    ("rb_colour_ignores_k", "oracle_rbgs_f64",
+     "if ((((i - h) + (j - h) + (k - h)) & 1) != color) continue;",
+     "if ((((i - h) + (j - h)) & 1) != color) continue;"),
+    ("rb_black_first", "oracle_rbgs_f64",
+     "for (int color = 0; color < 2; color++)", "for (int color = 1; color >= 0; color--)"),
+    ("rb_f32_dropped_ym", "oracle_rbgs_f32", "s = s + u[IDX(k, j - 1, i)];", ""),
     ("refine_f32_no_correction", "oracle_refine",
      "u[IDX(k, j, i)] = u[IDX(k, j, i)] + (double)e32[IDX(k, j, i)];",
      "u[IDX(k, j, i)] = u[IDX(k, j, i)] + 0.5 * (double)e32[IDX(k, j, i)];"),
