@@ -31,7 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-SECTIONS = ("copy", "small", "by_t", "fp32", "gs", "poisson", "serving")
+SECTIONS = ("copy", "small", "by_t", "fp32", "gs", "rbgs", "poisson", "serving")
 
 
 def bytes_per_lup(elem_bytes: int, t: int) -> float:
@@ -87,7 +87,7 @@ def parse():
     ap.add_argument("--quick", action="store_true", help="headline only (same as --sections none)")
     ap.add_argument("--sections", default="all",
                     help="extra measurements after the headline, comma separated: "
-                         "copy,small,by_t,fp32,gs,poisson,serving (or all / none)")
+                         "copy,small,by_t,fp32,gs,rbgs,poisson,serving (or all / none)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--poisson-n", type=int, default=256)
     ap.add_argument("--poisson-m", type=int, default=32, help="inner sweeps per outer round")
@@ -470,6 +470,16 @@ def main():
             log("gs 384^3 x50 %s: %s" % (key, gs[key]))
         extra["gs_384_x50"] = gs
         del ug, u0
+    if "rbgs" in sections:
+        # red-black Gauss-Seidel on the fused pass, 512^3 x 100 sweeps (FP64)
+        rb = {}
+        for t in (0, 1, 2, 3, 4):
+            jacobi_run_rb = lambda: P.red_black(u, s, S, t_fuse=t)
+            jacobi_run_rb()
+            m = events_time(torch, jacobi_run_rb, reps=2) / 2
+            rb[str(t)] = {"ms": round(m, 3), "MLUPs": round(lups_step / (m * 1e-3) / 1e6)}
+            log("red-black fp64 512^3 x%d t=%d: %s" % (S, t, rb[str(t)]))
+        extra["rbgs_fp64_512_x100_by_t"] = rb
     torch.cuda.synchronize()
     # free the 512^3 grids before the remaining measurements
     del u, s

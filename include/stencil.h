@@ -137,6 +137,25 @@ int stencil_gs(const st_grid *grid, int32_t dtype, void *u, const void *f, const
                int32_t bc, double bc_value, int32_t sweeps, int32_t t_fuse, void *hip_stream);
 
 /*
+ * stencil_rbgs -- `sweeps` red-black Gauss-Seidel sweeps: the alternative
+ * ordering the paper names next to the lexicographic one (Sec. 3).  A sweep
+ * updates, in place, every red site ((i + j + k) even, interior coordinates
+ * counted from 0) and then every black site, with the same update and
+ * operand order as stencil_gs; red sites read only old black values and
+ * black sites the new red ones.  Run on the fused pass of stencil_jacobi:
+ * one sweep is two time levels, so t_fuse (0 = automatic, else 1..4) sweeps
+ * are applied per pass over memory and the pass alternates between u and
+ * scratch.
+ *  Arguments as for stencil_jacobi (u, scratch same size and dtype, not
+ *  overlapping; result in u; stream-ordered).  Bit-identical to `sweeps`
+ *  sequential red-black sweeps for every t_fuse.  ST_EINVAL for t_fuse
+ *  outside 0..4 and the conditions listed for stencil_jacobi.
+ */
+int stencil_rbgs(const st_grid *grid, int32_t dtype, void *u, void *scratch, const void *f,
+                 const st_weights *w, int32_t bc, double bc_value, int32_t sweeps,
+                 int32_t t_fuse, void *hip_stream);
+
+/*
  * stencil_residual -- FP64 residual of the h^2-scaled Poisson system
  * A u = f' with A u = 6c - s (the a = 0, b = 1/6 smoother's operator):
  *     r = f' - ((6*c) - s)

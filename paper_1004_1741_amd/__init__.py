@@ -13,7 +13,7 @@ from __future__ import annotations
 import ctypes
 import pathlib
 
-__all__ = ["lib", "jacobi", "gauss_seidel", "residual", "refine_solve", "jacobi_plan",
+__all__ = ["lib", "jacobi", "gauss_seidel", "red_black", "residual", "refine_solve", "jacobi_plan",
            "StencilError", "SmoothService", "ST", "LIB_PATH"]
 
 LIB_PATH = pathlib.Path(__file__).resolve().parent / "libstencil.so"
@@ -79,6 +79,7 @@ SIGNATURES = [
     ("stencil_jacobi", _i32, [_P(Grid), _i32, _vp, _vp, _vp, _P(Weights), _i32, _dbl, _i32, _i32, _vp]),
     ("stencil_jacobi_plan", _i32, [_i32, _i32, _i32, _i32, _P(_i32), _P(_i32), _i32, _P(_i32)]),
     ("stencil_gs", _i32, [_P(Grid), _i32, _vp, _vp, _P(Weights), _i32, _dbl, _i32, _i32, _vp]),
+    ("stencil_rbgs", _i32, [_P(Grid), _i32, _vp, _vp, _vp, _P(Weights), _i32, _dbl, _i32, _i32, _vp]),
     ("stencil_residual", _i32, [_P(Grid), _vp, _vp, _vp, _P(_dbl), _vp]),
     ("stencil_refine_solve", _i32, [_P(Grid), _i32, _i32, _vp, _vp, _i32, _i32, _dbl, _i32,
                                     _P(_i32), _P(_dbl), _vp]),
@@ -183,6 +184,21 @@ def jacobi_plan(sweeps, t_fuse=0, fp32=False, rhs=False):
                                      int(t_fuse), ctypes.byref(n), buf, len(buf),
                                      ctypes.byref(fc)))
     return list(buf[:n.value]), bool(fc.value)
+
+
+def red_black(u, scratch, sweeps, a=0.0, b=1.0 / 6.0, f=None, g=0.0, t_fuse=0, halo=1,
+              bc=ST.BC_KEEP, bc_value=0.0, stream=None):
+    """`sweeps` red-black Gauss-Seidel sweeps on u (result in u), t_fuse sweeps
+    (1..4) per pass over memory."""
+    if scratch.shape != u.shape or scratch.dtype != u.dtype:
+        raise ValueError("scratch must match u")
+    _check_rhs(u, f, halo)
+    grid = _dims(u, halo)
+    w = Weights(a, b, g)
+    _check(lib().stencil_rbgs(ctypes.byref(grid), _dtype_code(u), _dev_ptr(u, "u"),
+                              _dev_ptr(scratch, "scratch"), _dev_ptr(f, "f"), ctypes.byref(w),
+                              bc, bc_value, int(sweeps), int(t_fuse), _stream(stream)))
+    return u
 
 
 def gauss_seidel(u, sweeps, a=0.0, b=1.0 / 6.0, f=None, g=0.0, t_fuse=0, halo=1,

@@ -56,6 +56,11 @@ hipError_t launch_jacobi_batch(bool fp32, int tb, bool has_a, bool has_f,
                                const std::vector<JacBatchItem> &items, void *table_dev,
                                std::vector<unsigned char> &host_buf, hipStream_t s);
 
+// One fused red-black Gauss-Seidel pass: dst <- sweeps (1..4) red-black
+// sweeps of src, as 2*sweeps levels of the fused pass.
+hipError_t launch_rbgs_pass(bool fp32, int sweeps, const Geom &g, const void *src, void *dst,
+                            const void *f, double a, double b, double gw, hipStream_t s);
+
 // The fused pass for one level count TB (1..8); each TB is compiled in its
 // own translation unit, the functions above dispatch on tb.
 template <int TB>
@@ -63,6 +68,9 @@ struct JacobiLevels {
     static JacTileCfg cfg(bool fp32);
     static hipError_t pass(bool fp32, const Geom &g, const void *src, void *dst, const void *f,
                            double a, double b, double gw, int zc, hipStream_t s);
+    // red-black Gauss-Seidel: TB/2 sweeps in one pass (TB even)
+    static hipError_t rb_pass(bool fp32, const Geom &g, const void *src, void *dst,
+                              const void *f, double a, double b, double gw, hipStream_t s);
     static hipError_t batch(bool fp32, bool has_a, bool has_f,
                             const std::vector<JacBatchItem> &items, void *table_dev,
                             std::vector<unsigned char> &host_buf, hipStream_t s);

@@ -43,6 +43,17 @@ hipError_t launch_jacobi_pass(bool fp32, int tb, const Geom &g, const void *src,
     }
 }
 
+hipError_t launch_rbgs_pass(bool fp32, int sweeps, const Geom &g, const void *src, void *dst,
+                            const void *f, double a, double b, double gw, hipStream_t s) {
+    switch (sweeps) {
+        case 1: return JacobiLevels<2>::rb_pass(fp32, g, src, dst, f, a, b, gw, s);
+        case 2: return JacobiLevels<4>::rb_pass(fp32, g, src, dst, f, a, b, gw, s);
+        case 3: return JacobiLevels<6>::rb_pass(fp32, g, src, dst, f, a, b, gw, s);
+        case 4: return JacobiLevels<8>::rb_pass(fp32, g, src, dst, f, a, b, gw, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 size_t jacobi_batch_table_bytes(int njobs) { return JacobiLevels<1>::table_bytes(njobs); }
 
 hipError_t launch_jacobi_batch(bool fp32, int tb, bool has_a, bool has_f,

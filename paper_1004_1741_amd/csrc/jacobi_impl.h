@@ -132,7 +132,14 @@ struct FRing {
     static constexpr size_t alloc = on ? ring_elems : 1;
 };
 
-template <typename T, int TB, int VX, int RY, int NW, bool HAS_A, bool HAS_F, bool EDGE>
+// RB: red-black Gauss-Seidel.  Level tau updates only the sites of colour
+// (tau - 1) & 1 (colour = parity of (x-h) + (y-h) + (z-h)) and copies the
+// others from level tau-1; axis neighbours have the other colour, so two
+// levels are one red-black sweep.  Level tau produces plane s - tau at step
+// s, so the updated colour at step s is the same for every level: a site is
+// updated at step s iff x + y + s - 3h + 1 is even.
+template <typename T, int TB, int VX, int RY, int NW, bool HAS_A, bool HAS_F, bool EDGE,
+          bool RB = false>
 __device__ __forceinline__ void jacobi_tile(const JacArgs<T> &A, int tx, int ty, int cz,
                                             T (*xch)[TB][NW][2][64 * VX], T *fring) {
     constexpr bool RING = FRing<T, TB, VX, RY, NW, HAS_F>::on;
@@ -267,6 +274,8 @@ __device__ __forceinline__ void jacobi_tile(const JacArgs<T> &A, int tx, int ty,
     auto step = [&](int s, T (&Aa)[TB][RY][VX], T (&Bb)[TB][RY][VX],
                     T (&Fc)[FPRE ? RY : 1][VX], T (&Fn)[FPRE ? RY : 1][VX], auto full_c) {
         constexpr bool FULL = decltype(full_c)::value;
+        // red-black: parity of the sites this step updates, for (r, v) = (0, 0)
+        const int rbp = RB ? ((x0 + y0 + s + 1 - 3 * h) & 1) : 0;
         T Nprev[RY][VX];  // new plane of level tau-1 (level 0: plane s, loaded)
 #pragma unroll
         for (int r = 0; r < RY; ++r)
@@ -341,6 +350,7 @@ __device__ __forceinline__ void jacobi_tile(const JacArgs<T> &A, int tx, int ty,
                         else
                             val = A.b * sum;
                         if constexpr (HAS_F) val = val + (A.g * fv[r][v]);
+                        if constexpr (RB) val = ((rbp + r + v) & 1) ? c : val;
                         if constexpr (EDGE) {
                             const bool up = (updy >> r & 1u) && (updx >> v & 1u);
                             val = up ? val : c;
@@ -406,7 +416,7 @@ __device__ __forceinline__ void jacobi_tile(const JacArgs<T> &A, int tx, int ty,
     if (s <= s_end) step(s, P0, P1, F0, F1, Part{});
 }
 
-template <typename T, int TB, int VX, int RY, int NW, bool HAS_A, bool HAS_F>
+template <typename T, int TB, int VX, int RY, int NW, bool HAS_A, bool HAS_F, bool RB = false>
 __global__ void __launch_bounds__(NW * 64) jacobi_pass_kernel(JacArgs<T> A) {
     __shared__ T xch[2][TB][NW][2][64 * VX];
     __shared__ T fring[FRing<T, TB, VX, RY, NW, HAS_F>::alloc];
@@ -432,9 +442,9 @@ __global__ void __launch_bounds__(NW * 64) jacobi_pass_kernel(JacArgs<T> A) {
     const bool interior = xs >= A.h && xs + 64 * VX <= A.h + A.nx && ys >= A.h &&
                           ys + NW * RY <= A.h + A.ny;
     if (interior)
-        jacobi_tile<T, TB, VX, RY, NW, HAS_A, HAS_F, false>(A, tx, ty, cz, xch, fring);
+        jacobi_tile<T, TB, VX, RY, NW, HAS_A, HAS_F, false, RB>(A, tx, ty, cz, xch, fring);
     else
-        jacobi_tile<T, TB, VX, RY, NW, HAS_A, HAS_F, true>(A, tx, ty, cz, xch, fring);
+        jacobi_tile<T, TB, VX, RY, NW, HAS_A, HAS_F, true, RB>(A, tx, ty, cz, xch, fring);
 }
 
 // Batched pass: one launch advances several independent grids (jobs of the
@@ -549,7 +559,7 @@ int choose_chunks(const JacTileCfg &c, const Geom &g, int tiles_xy, int resident
     return best;
 }
 
-template <typename T, int TB, bool HAS_A, bool HAS_F>
+template <typename T, int TB, bool HAS_A, bool HAS_F, bool RB = false>
 int resident_wgs(bool batch) {
     using C = Cfg<T, TB, HAS_F>;
     static int cached[2] = {0, 0};
@@ -560,7 +570,7 @@ int resident_wgs(bool batch) {
             batch ? reinterpret_cast<const void *>(
                         jacobi_batch_kernel<T, TB, C::VX, C::RY, C::NW, HAS_A, HAS_F>)
                   : reinterpret_cast<const void *>(
-                        jacobi_pass_kernel<T, TB, C::VX, C::RY, C::NW, HAS_A, HAS_F>);
+                        jacobi_pass_kernel<T, TB, C::VX, C::RY, C::NW, HAS_A, HAS_F, RB>);
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, C::NW * 64, 0) !=
                 hipSuccess || per_cu < 1)
             per_cu = 1;
@@ -600,14 +610,14 @@ JacArgs<T> make_args(const Geom &g, const void *src, void *dst, const void *f, d
     return A;
 }
 
-template <typename T, int TB, bool HAS_A, bool HAS_F>
+template <typename T, int TB, bool HAS_A, bool HAS_F, bool RB = false>
 hipError_t launch_t(const Geom &g, const void *src, void *dst, const void *f, double a, double b,
                     double gw, int zc, hipStream_t s) {
     using C = Cfg<T, TB, HAS_F>;
     const JacArgs<T> A = make_args<T, TB, HAS_F>(g, src, dst, f, a, b, gw, zc,
-                                          resident_wgs<T, TB, HAS_A, HAS_F>(false));
+                                          resident_wgs<T, TB, HAS_A, HAS_F, RB>(false));
     const int grid = ((A.ntiles + 7) / 8) * 8;
-    hipLaunchKernelGGL((jacobi_pass_kernel<T, TB, C::VX, C::RY, C::NW, HAS_A, HAS_F>),
+    hipLaunchKernelGGL((jacobi_pass_kernel<T, TB, C::VX, C::RY, C::NW, HAS_A, HAS_F, RB>),
                        dim3(grid), dim3(C::NW * 64), 0, s, A);
     return hipGetLastError();
 }
@@ -645,14 +655,14 @@ hipError_t launch_batch_tb(bool ha, bool hf, const std::vector<JacBatchItem> &it
     return launch_batch_t<T, TB, false, false>(items, table_dev, hb, s);
 }
 
-template <typename T, int TB>
+template <typename T, int TB, bool RB = false>
 hipError_t launch_tb(const Geom &g, const void *src, void *dst, const void *f, double a,
                      double b, double gw, int zc, hipStream_t s) {
     const bool ha = (a != 0.0), hf = (f != nullptr);
-    if (ha && hf) return launch_t<T, TB, true, true>(g, src, dst, f, a, b, gw, zc, s);
-    if (ha) return launch_t<T, TB, true, false>(g, src, dst, f, a, b, gw, zc, s);
-    if (hf) return launch_t<T, TB, false, true>(g, src, dst, f, a, b, gw, zc, s);
-    return launch_t<T, TB, false, false>(g, src, dst, f, a, b, gw, zc, s);
+    if (ha && hf) return launch_t<T, TB, true, true, RB>(g, src, dst, f, a, b, gw, zc, s);
+    if (ha) return launch_t<T, TB, true, false, RB>(g, src, dst, f, a, b, gw, zc, s);
+    if (hf) return launch_t<T, TB, false, true, RB>(g, src, dst, f, a, b, gw, zc, s);
+    return launch_t<T, TB, false, false, RB>(g, src, dst, f, a, b, gw, zc, s);
 }
 
 }  // namespace
@@ -668,6 +678,18 @@ hipError_t JacobiLevels<TB>::pass(bool fp32, const Geom &g, const void *src, voi
                                   hipStream_t s) {
     return fp32 ? launch_tb<float, TB>(g, src, dst, f, a, b, gw, zc, s)
                 : launch_tb<double, TB>(g, src, dst, f, a, b, gw, zc, s);
+}
+
+template <int TB>
+hipError_t JacobiLevels<TB>::rb_pass(bool fp32, const Geom &g, const void *src, void *dst,
+                                     const void *f, double a, double b, double gw,
+                                     hipStream_t s) {
+    if constexpr (TB % 2 != 0) {
+        return hipErrorInvalidValue;  // a red-black sweep is two levels
+    } else {
+        return fp32 ? launch_tb<float, TB, true>(g, src, dst, f, a, b, gw, 0, s)
+                    : launch_tb<double, TB, true>(g, src, dst, f, a, b, gw, 0, s);
+    }
 }
 
 template <int TB>

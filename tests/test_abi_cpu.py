@@ -68,6 +68,23 @@ def test_jacobi_validation(P, kw, status):
     assert L.stencil_last_error()
 
 
+@pytest.mark.parametrize("kw,status", [
+    (dict(nx=0), -1), (dict(dtype=7), -1), (dict(u=None), -1), (dict(scratch=None), -1),
+    (dict(t=5), -1), (dict(t=-1), -1), (dict(sweeps=-1), -1), (dict(bc=9), -1),
+    (dict(overlap=True), -1), (dict(w=None), -1),
+])
+def test_rbgs_validation(P, kw, status):
+    L = P.lib()
+    g = _grid(P, nx=kw.get("nx", 8))
+    w = None if "w" in kw else ctypes.byref(P.Weights(0.0, 1.0 / 6.0, 0.0))
+    u = kw.get("u", FAKE)
+    s = FAKE if kw.get("overlap") else kw.get("scratch", FAKE2)
+    rc = L.stencil_rbgs(ctypes.byref(g), kw.get("dtype", 0), u, s, None, w, kw.get("bc", 0), 0.0,
+                        kw.get("sweeps", 1), kw.get("t", 0), None)
+    assert rc == status
+    assert L.stencil_last_error()
+
+
 @pytest.mark.parametrize("kw", [dict(nz=0), dict(dtype=2), dict(u=None), dict(t=11),
                                 dict(sweeps=-3), dict(ny=9000)])
 def test_gs_validation(P, kw):

@@ -100,6 +100,48 @@ def test_jacobi_split_invariance(P, olib):
     assert_same(a, b, "7+6 vs 13 sweeps")
 
 
+# --- red-black Gauss-Seidel on the fused pass ----------------------------------
+
+def _run_rbgs(P, u, sweeps, t, a=0.0, b=1.0 / 6.0, f=None, g=0.0, h=1):
+    du = to_dev(u)
+    ds = to_dev(np.zeros_like(u))
+    df = None if f is None else to_dev(f)
+    P.red_black(du, ds, sweeps, a=a, b=b, f=df, g=g, t_fuse=t, halo=h)
+    return to_host(du)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("case", JAC_CASES, ids=lambda c: "x".join(map(str, c)))
+def test_rbgs_ragged(P, olib, case, dtype):
+    nx, ny, nz, h, S = case
+    dt = np.float64 if dtype == "f64" else np.float32
+    u = si.uniform_padded(nx, ny, nz, h, seed=nx + 5 * nz, lo=-1.0, hi=1.0).astype(dt)
+    f = si.uniform_rhs(nx, ny, nz, seed=4).astype(dt)
+    for t in range(0, 5):
+        for (a, b, g, ff) in ((0.0, 1.0 / 6.0, 0.0, None), (0.3, 0.1, 0.25, f),
+                              (0.0, 1.0 / 6.0, 1.0 / 6.0, f)):
+            say("red-black", case, dtype, "t=%d a=%g rhs=%s" % (t, a, ff is not None))
+            ref = oracle.red_black(u, S, a=a, b=b, f=ff, g=g, h=h, lib=olib)
+            got = _run_rbgs(P, u, S, t, a=a, b=b, f=ff, g=g, h=h)
+            assert_same(got, ref, "red-black %s %s t=%d a=%g" % (case, dtype, t, a))
+
+
+def test_rbgs_several_tiles_and_chunks(P, olib):
+    """160 x 150 x 140 (ragged in every direction, several tiles and z-chunks),
+    20 sweeps at the automatic depth and at 4 sweeps per pass."""
+    u = si.uniform_padded(160, 150, 140, 1, seed=11)
+    ref = oracle.red_black(u, 20, lib=olib)
+    for t in (0, 4):
+        say("red-black 160x150x140 x20 t=%d" % t)
+        assert_same(_run_rbgs(P, u, 20, t), ref, "red-black 160x150x140 t=%d" % t)
+
+
+def test_rbgs_differs_from_lexicographic(P, olib):
+    u = si.uniform_padded(30, 20, 10, 1, seed=2)
+    got = _run_rbgs(P, u, 3, 0)
+    assert not np.array_equal(got, oracle.gauss_seidel(u, 3, lib=olib))
+
+
 # --- full size: 512^3, 100 sweeps, sampled against the oracle -----------------
 
 @pytest.mark.parametrize("t", [4, 5, 8])
