@@ -91,7 +91,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--poisson-n", type=int, default=256)
     ap.add_argument("--poisson-m", type=int, default=32, help="inner sweeps per outer round")
-    ap.add_argument("--poisson-methods", default="jacobi,gs")
+    ap.add_argument("--poisson-methods", default="jacobi,gs,rbgs")
     ap.add_argument("--serving-jobs", type=int, default=300)
     ap.add_argument("--serving-rate", default="200",
                     help="arrival rate(s) per second, comma separated")
@@ -252,7 +252,7 @@ def small_grids(P, torch):
     return out
 
 
-def poisson_compare(P, torch, n, seed=0, methods=(0, 1), m=32, tol=1e-10, chunk_s=30.0):
+def poisson_compare(P, torch, n, seed=0, methods=(0, 1, 2), m=32, tol=1e-10, chunk_s=30.0):
     """-Laplace u = f on n^3, h = 1/(n+1), f U[-1,1), u0 = 0: time to reach
     ||f' - A u|| <= tol ||f'|| with the FP32-refined loop and the plain FP64
     method.  The solve runs as consecutive library calls of a bounded number
@@ -264,7 +264,7 @@ def poisson_compare(P, torch, n, seed=0, methods=(0, 1), m=32, tol=1e-10, chunk_
     fp = torch.from_numpy(w["f"] / float((n + 1) ** 2)).to("cuda")
     out = {}
     for method in methods:
-        name = "jacobi" if method == 0 else "gauss_seidel"
+        name = ("jacobi", "gauss_seidel", "red_black")[method]
         res = {}
         for inner_fp32, key in ((True, "fp32_refined"), (False, "plain_fp64")):
             u = torch.from_numpy(w["u"]).to("cuda")
@@ -485,7 +485,7 @@ def main():
     del u, s
     torch.cuda.empty_cache()
     if "poisson" in sections and args.poisson_n > 0:
-        names = {"jacobi": 0, "gs": 1}
+        names = {"jacobi": 0, "gs": 1, "rbgs": 2}
         methods = tuple(names[x] for x in args.poisson_methods.split(","))
         extra["poisson_%d" % args.poisson_n] = poisson_compare(P, torch, args.poisson_n,
                                                                methods=methods, m=args.poisson_m)

@@ -179,7 +179,8 @@ int stencil_residual(const st_grid *grid, const double *u, const double *fp, dou
  *      loop: r = f' - A u; stop when rel <= rel_tol;
  *            u = inner_sweeps FP64 sweeps of the method on u itself with the
  *                right-hand side f' and weights (0, 1/6, 1/6).
- *  method      0 = Jacobi, 1 = Gauss-Seidel.
+ *  method      0 = Jacobi, 1 = Gauss-Seidel, 2 = red-black Gauss-Seidel
+ *              (t_fuse then 0..4 sweeps per pass).
  *  u           FP64 grid: initial guess in, solution out; ghosts = Dirichlet.
  *  fp          interior-only FP64 right-hand side (h^2 f).
  *  t_fuse      fused sweeps per pass of the inner smoother (0 = automatic,

@@ -362,7 +362,8 @@ int oracle_defect_f64(int64_t nx, int64_t ny, int64_t nz, int64_t h, const doubl
 /* -------------------------------------------------- iterative refinement ---- */
 
 /* Defect-correction loop for the h^2-scaled Poisson system (method 0 =
- * Jacobi, 1 = Gauss-Seidel as the inner smoother):
+ * Jacobi, 1 = lexicographic Gauss-Seidel, 2 = red-black Gauss-Seidel as the
+ * inner smoother):
  *     loop: r = f' - A u; stop when ||r||/||f'|| <= tol;
  *           e = m sweeps of the smoother on A e = r from e = 0, zero ghosts,
  *               weights (a, b, g) = (0, 1/6, 1/6);
@@ -396,6 +397,8 @@ int oracle_refine(int64_t nx, int64_t ny, int64_t nz, int64_t h, int method, dou
             memset(e32, 0, (size_t)n * sizeof(float));
             if (method == 0)
                 oracle_jacobi_f32(nx, ny, nz, h, e32, r32, 0.0, 1.0 / 6.0, 1.0 / 6.0, m);
+            else if (method == 2)
+                oracle_rbgs_f32(nx, ny, nz, h, e32, r32, 0.0, 1.0 / 6.0, 1.0 / 6.0, m);
             else
                 oracle_gs_f32(nx, ny, nz, h, e32, r32, 0.0, 1.0 / 6.0, 1.0 / 6.0, m);
             for (int64_t k = h; k < h + nz; k++)
@@ -406,6 +409,8 @@ int oracle_refine(int64_t nx, int64_t ny, int64_t nz, int64_t h, int method, dou
             memset(e, 0, (size_t)n * sizeof(double));
             if (method == 0)
                 oracle_jacobi_f64(nx, ny, nz, h, e, r, 0.0, 1.0 / 6.0, 1.0 / 6.0, m);
+            else if (method == 2)
+                oracle_rbgs_f64(nx, ny, nz, h, e, r, 0.0, 1.0 / 6.0, 1.0 / 6.0, m);
             else
                 oracle_gs_f64(nx, ny, nz, h, e, r, 0.0, 1.0 / 6.0, 1.0 / 6.0, m);
             for (int64_t k = h; k < h + nz; k++)
@@ -440,6 +445,8 @@ int oracle_refined_job(int64_t nx, int64_t ny, int64_t nz, int64_t h, int method
     for (int64_t q = 0; q < ni; q++) r32[q] = (float)r[q];
     if (method == 0)
         oracle_jacobi_f32(nx, ny, nz, h, e32, r32, a, b, 1.0, sweeps);
+    else if (method == 2)
+        oracle_rbgs_f32(nx, ny, nz, h, e32, r32, a, b, 1.0, sweeps);
     else
         oracle_gs_f32(nx, ny, nz, h, e32, r32, a, b, 1.0, sweeps);
     for (int64_t k = h; k < h + nz; k++)

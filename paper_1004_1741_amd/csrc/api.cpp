@@ -121,9 +121,10 @@ int run_jacobi(const Geom &g, bool fp32, void *u, void *scratch, const void *f, 
 
 // Red-black sweeps per pass: at most 4 (8 levels on chip).  Automatic: 3
 // (6 levels; FP64 512^3 x 100 on MI355X: t=1 50.0 ms, 2: 31.4, 3: 30.5,
-// 4: 41.2).
-int rb_sweeps_per_pass(int t_fuse) {
-    int t = t_fuse == 0 ? 3 : t_fuse;
+// 4: 41.2), except FP64 with a right-hand side, where only 4 levels keep the
+// f ring in LDS (as for Jacobi with f, whose best depth is 4): 2.
+int rb_sweeps_per_pass(int t_fuse, bool fp32, bool rhs) {
+    int t = t_fuse == 0 ? ((!fp32 && rhs) ? 2 : 3) : t_fuse;
     return t > 4 ? 4 : t;
 }
 
@@ -133,7 +134,8 @@ int run_rbgs(const Geom &g, bool fp32, void *u, void *scratch, const void *f, do
     bool fc = false;
     // the same schedule rule as Jacobi, counted in red-black sweeps
     std::vector<int> plan =
-        jacobi_plan(fp32 ? ST_FP32 : ST_FP64, f != nullptr, sweeps, rb_sweeps_per_pass(t_fuse), &fc);
+        jacobi_plan(fp32 ? ST_FP32 : ST_FP64, f != nullptr, sweeps,
+                    rb_sweeps_per_pass(t_fuse, fp32, f != nullptr), &fc);
     HIP_TRY(launch_copy_ghosts(fp32, g, u, scratch, s), "ghost copy");
     const void *src = u;
     void *dst = scratch;
@@ -311,13 +313,15 @@ int stencil_refine_solve(const st_grid *grid, int32_t method, int32_t inner_dtyp
     Geom g;
     int rc = check_grid(grid, &g);
     if (rc) return rc;
-    if (method != 0 && method != 1) return fail(ST_EINVAL, "method must be 0 (Jacobi) or 1 (GS)");
+    if (method < 0 || method > 2)
+        return fail(ST_EINVAL, "method must be 0 (Jacobi), 1 (GS) or 2 (red-black GS)");
     if (inner_dtype != ST_FP64 && inner_dtype != ST_FP32)
         return fail(ST_EINVAL, "inner_dtype must be FP64 or FP32");
     if (!u || !fp) return fail(ST_EINVAL, "u and fp must be device pointers");
     if (inner_sweeps < 1) return fail(ST_EINVAL, "inner_sweeps must be >= 1");
     if (max_outer < 0) return fail(ST_EINVAL, "max_outer must be >= 0");
     if (!valid_t(t_fuse)) return fail(ST_EINVAL, "t_fuse must be 0..8 or 16");
+    if (method == 2 && t_fuse > 4) return fail(ST_EINVAL, "t_fuse must be 0..4 for red-black");
     if (!(rel_tol >= 0.0)) return fail(ST_EINVAL, "rel_tol must be >= 0");
     if (method == 1 && (g.ny > 8192 || g.nz > 8192))
         return fail(ST_EINVAL, "Gauss-Seidel supports ny, nz <= 8192");
@@ -333,8 +337,8 @@ int stencil_refine_solve(const st_grid *grid, int32_t method, int32_t inner_dtyp
     if (f32) {
         HIP_TRY(rbuf.alloc((size_t)ni * sizeof(float)), "refine workspace");
         HIP_TRY(ebuf.alloc((size_t)np * sizeof(float)), "refine workspace");
-        if (method == 0) HIP_TRY(sbuf.alloc((size_t)np * sizeof(float)), "refine workspace");
-    } else if (method == 0) {
+        if (method != 1) HIP_TRY(sbuf.alloc((size_t)np * sizeof(float)), "refine workspace");
+    } else if (method != 1) {
         HIP_TRY(sbuf.alloc((size_t)np * sizeof(double)), "refine workspace");
     }
     // ||f'|| with the same deterministic reduction (residual of u = 0 is f')
@@ -377,6 +381,9 @@ int stencil_refine_solve(const st_grid *grid, int32_t method, int32_t inner_dtyp
             if (method == 0)
                 rc = run_jacobi(g, true, ebuf.p, sbuf.p, rbuf.p, pw.center, pw.neighbor, pw.rhs,
                                 inner_sweeps, t_fuse, s);
+            else if (method == 2)
+                rc = run_rbgs(g, true, ebuf.p, sbuf.p, rbuf.p, pw.center, pw.neighbor, pw.rhs,
+                              inner_sweeps, t_fuse, s);
             else
                 rc = run_gs(g, true, ebuf.p, rbuf.p, pw.center, pw.neighbor, pw.rhs,
                             inner_sweeps, t_fuse, s);
@@ -387,6 +394,9 @@ int stencil_refine_solve(const st_grid *grid, int32_t method, int32_t inner_dtyp
             if (method == 0)
                 rc = run_jacobi(g, false, u, sbuf.p, fp, pw.center, pw.neighbor, pw.rhs,
                                 inner_sweeps, t_fuse, s);
+            else if (method == 2)
+                rc = run_rbgs(g, false, u, sbuf.p, fp, pw.center, pw.neighbor, pw.rhs,
+                              inner_sweeps, t_fuse, s);
             else
                 rc = run_gs(g, false, u, fp, pw.center, pw.neighbor, pw.rhs, inner_sweeps,
                             t_fuse, s);

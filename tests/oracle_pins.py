@@ -240,7 +240,7 @@ def pin_defect_correction(lib):
     fp = (2 * rng.random((n, n, n)) - 1) / (n + 1) ** 2
     u0 = np.zeros((n + 2, n + 2, n + 2))
     u0[1:-1, 1:-1, 1:-1] = rng.random((n, n, n)) * 1e-3
-    for method in (0, 1):
+    for method in (0, 1, 2):
         m = 12
         out, rc, outer, _ = oracle.refine(u0, fp, method=method, inner_f32=False, m=m,
                                           tol=0.0, max_outer=1, lib=lib)
@@ -264,7 +264,7 @@ def pin_manufactured_solution(lib):
     mu = 6.0 - 6.0 * math.cos(math.pi / (n + 1))
     fp = mu * us[1:-1, 1:-1, 1:-1]
     u0 = np.zeros_like(us)
-    for method in (0, 1):
+    for method in (0, 1, 2):
         for inner_f32 in (False, True):
             out, rc, outer, rel = oracle.refine(u0, fp, method=method, inner_f32=inner_f32, m=16,
                                                 tol=1e-10, max_outer=400, lib=lib)
@@ -277,6 +277,10 @@ def pin_manufactured_solution(lib):
     _, _, og, _ = oracle.refine(u0, fp + 1e-3, method=1, inner_f32=False, m=8, tol=1e-10,
                                 max_outer=2000, lib=lib)
     assert 0.4 <= og / oj <= 0.62, (oj, og)
+    # red-black has the same asymptotic factor as lexicographic GS
+    _, _, orb, _ = oracle.refine(u0, fp + 1e-3, method=2, inner_f32=False, m=8, tol=1e-10,
+                                 max_outer=2000, lib=lib)
+    assert 0.4 <= orb / oj <= 0.62, (oj, orb)
 
 
 def pin_split_invariance(lib):

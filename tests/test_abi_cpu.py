@@ -101,7 +101,8 @@ def test_refine_and_residual_validation(P):
     g = _grid(P)
     od, rel = ctypes.c_int32(0), ctypes.c_double(0)
     args = dict(method=0, dt=1, u=FAKE, fp=FAKE2, m=4, t=0, tol=1e-10, mo=5)
-    for bad in (dict(method=2), dict(dt=3), dict(u=None), dict(fp=None), dict(m=0), dict(t=10),
+    for bad in (dict(method=3), dict(method=2, t=5), dict(dt=3), dict(u=None), dict(fp=None),
+                dict(m=0), dict(t=10),
                 dict(tol=-1.0), dict(mo=-1)):
         a = dict(args, **bad)
         rc = L.stencil_refine_solve(ctypes.byref(g), a["method"], a["dt"], a["u"], a["fp"], a["m"],

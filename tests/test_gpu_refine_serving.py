@@ -52,7 +52,7 @@ def test_residual_parity(P, olib, dims):
 
 # --- refinement ---------------------------------------------------------------
 
-@pytest.mark.parametrize("method", [0, 1])
+@pytest.mark.parametrize("method", [0, 1, 2])
 def test_refine_fp32_inner_fixed_steps(P, olib, method):
     """Three defect-correction steps, bit-exact against the oracle's loop."""
     u0, fp = _poisson((20, 17, 13), seed=3)
@@ -68,7 +68,7 @@ def test_refine_fp32_inner_fixed_steps(P, olib, method):
     assert abs(grel - rel) <= 1e-12 * rel
 
 
-@pytest.mark.parametrize("method", [0, 1])
+@pytest.mark.parametrize("method", [0, 1, 2])
 def test_refine_plain_fp64_fixed_steps(P, olib, method):
     """The plain FP64 method: m sweeps of the smoother with f' between checks."""
     u0, fp = _poisson((18, 11, 16), seed=5)
@@ -82,7 +82,7 @@ def test_refine_plain_fp64_fixed_steps(P, olib, method):
     assert_same(to_host(du), ref, "plain fp64 method=%d" % method)
 
 
-@pytest.mark.parametrize("method", [0, 1])
+@pytest.mark.parametrize("method", [0, 1, 2])
 def test_refine_converges(P, olib, method):
     """FP32-refined solve reaches 1e-10; the oracle's residual of the GPU
     solution confirms it; the solution matches the plain FP64 solution."""
