@@ -136,6 +136,35 @@ def test_rbgs_several_tiles_and_chunks(P, olib):
         assert_same(_run_rbgs(P, u, 20, t), ref, "red-black 160x150x140 t=%d" % t)
 
 
+@pytest.mark.parametrize("t", [0, 4])
+def test_rbgs_512_sampled(P, olib, t):
+    """The 512^3 grid of the benchmark, its tiling and z-chunks, 10 red-black
+    sweeps, checked on 5^3 blocks of crops the oracle can afford.  A red-black
+    sweep moves information two sites (red from black, black from the new
+    red), so sites more than 2S from a cut face are exact; the crop origin
+    keeps the colouring (crop and grid interior coordinates differ by an even
+    sum)."""
+    w = si.jacobi_512(seed=0)
+    u = w["u"]
+    S = 10
+    say("red-black 512^3 x%d t=%d (GPU)" % (S, t))
+    got = _run_rbgs(P, u, S, t)
+    n = u.shape[0]
+    m = 2 * S + 4  # block half-width 2, plus 2S + 2 to the cut faces
+    for c in [(1, 1, 1), (1, n - 2, n // 2), (n // 2, n // 2, n // 2), (n - 2, 200, n - 2),
+              (300, 1, 17), (77, 301, 455)]:
+        lo = [max(0, x - m) for x in c]
+        if sum(lo) % 2:  # keep the colouring: move one origin by one site
+            ax = next(a for a in range(3) if lo[a] > 0) if any(lo) else 0
+            lo[ax] -= 1
+        sl = tuple(slice(lo[a], min(n, c[a] + m + 1)) for a in range(3))
+        sub = np.ascontiguousarray(u[sl])
+        blk = tuple(slice(max(0, c[a] - lo[a] - 2), c[a] - lo[a] + 3) for a in range(3))
+        ref = oracle.red_black(sub, S, lib=olib)
+        assert_same(got[sl][blk], ref[blk], "red-black 512^3 sample %s t=%d" % (c, t))
+    assert np.isfinite(got).all()
+
+
 def test_rbgs_differs_from_lexicographic(P, olib):
     u = si.uniform_padded(30, 20, 10, 1, seed=2)
     got = _run_rbgs(P, u, 3, 0)
