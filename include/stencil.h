@@ -213,7 +213,7 @@ typedef struct {
     uint64_t hbm_budget_bytes;  /* device pool size; jobs must fit inside it */
     int32_t max_inflight;       /* resident jobs at most (>= 1) */
     int32_t device;             /* HIP device ordinal */
-    int32_t t_fuse;             /* fused sweeps per Jacobi pass (0 = automatic) */
+    int32_t t_fuse;             /* fused sweeps per Jacobi pass (0 = automatic, 1..8, 16) */
     int32_t reserved;
 } smooth_config;
 

@@ -1,6 +1,7 @@
 // api.cpp -- the C ABI of libstencil (include/stencil.h): argument checks,
-// the Jacobi pass schedule, and the refinement loop.  All numerical work is
-// done by the HIP kernels in jacobi.hip, gs.hip and aux.hip.
+// the pass schedules, and the refinement loop.  All numerical work is done by
+// the HIP kernels of jacobi_impl.h (one unit per depth, jacobi_t<N>.hip),
+// gs.hip and aux.hip.
 #include <hip/hip_runtime.h>
 
 #include <cmath>

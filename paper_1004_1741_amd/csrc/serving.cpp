@@ -431,9 +431,8 @@ int smooth_init(const smooth_config *cfg, smooth_ctx **out) {
     if (!cfg || !out) return fail(ST_EINVAL, "config and out must not be NULL");
     if (cfg->max_inflight < 1) return fail(ST_EINVAL, "max_inflight must be >= 1");
     if (cfg->hbm_budget_bytes < 4096) return fail(ST_EINVAL, "hbm_budget_bytes too small");
-    if (!(cfg->t_fuse == 0 || cfg->t_fuse == 1 || cfg->t_fuse == 2 || cfg->t_fuse == 4 ||
-          cfg->t_fuse == 8 || cfg->t_fuse == 16))
-        return fail(ST_EINVAL, "t_fuse must be 0, 1, 2, 4, 8 or 16");
+    if (!((cfg->t_fuse >= 0 && cfg->t_fuse <= 8) || cfg->t_fuse == 16))
+        return fail(ST_EINVAL, "t_fuse must be 0..8 or 16");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev)
         return fail(ST_EINVAL, "no such HIP device");

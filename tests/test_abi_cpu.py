@@ -119,7 +119,7 @@ def test_service_validation(P):
     ctx = ctypes.c_void_p(None)
     assert L.smooth_init(ctypes.byref(P.SmoothConfig(1 << 20, 0, 0, 0, 0)),
                          ctypes.byref(ctx)) == P.ST.EINVAL
-    assert L.smooth_init(ctypes.byref(P.SmoothConfig(1 << 20, 4, 0, 3, 0)),
+    assert L.smooth_init(ctypes.byref(P.SmoothConfig(1 << 20, 4, 0, 9, 0)),
                          ctypes.byref(ctx)) == P.ST.EINVAL
     assert L.smooth_init(None, ctypes.byref(ctx)) == P.ST.EINVAL
     jid = ctypes.c_uint64(0)
