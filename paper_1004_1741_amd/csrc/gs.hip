@@ -51,6 +51,11 @@ constexpr int GS_RING = 32;   // ring positions per staged line (4 chunks)
 constexpr int GS_S = 41;      // LDS stride per line: S = 9 (mod 16) makes the
                               // 64 lanes' reads hit distinct banks
 constexpr int GS_SLOTS = 100; // 10 x 10 staged lines (corners unused)
+// The ring holds slots 1..98 only (slots 0 and 99 are unused corners) and the
+// last one needs no stride padding: 97 * 41 + 32 values, 32072 bytes in FP64,
+// so five workgroups fit the 160 KB of LDS of a CU instead of four.
+constexpr int GS_SLOT0 = 1;
+constexpr int GS_RING_LEN = (GS_SLOTS - 2 - GS_SLOT0) * GS_S + GS_RING;
 
 template <typename T>
 struct GsJob {
@@ -126,7 +131,7 @@ __device__ __forceinline__ void gs_item(const GsJob<T> &A, int tau, int J, int K
     const int lane = threadIdx.x;
     const int kk = lane & 7, jj = lane >> 3;  // kk fastest: conflict-free LDS
     const int d = jj + kk;                    // skew of this lane's line
-    const int own = (kk + 1) * 10 + (jj + 1);
+    const int own = (kk + 1) * 10 + (jj + 1) - GS_SLOT0;  // ring slot of this lane's line
     const int fown = kk * 10 + jj;
     const int h = A.h;
         const int j0 = h + 8 * J, k0 = h + 8 * K;
@@ -156,7 +161,7 @@ __device__ __forceinline__ void gs_item(const GsJob<T> &A, int tau, int J, int K
             const T *l0 = A.u + (int64_t)kg * A.plane + (int64_t)jg * A.px + h;
             lsh[m] = (int)((reinterpret_cast<uintptr_t>(l0) / sizeof(T)) & (GS_C - 1));
             lsrc[m] = l0 + (e & 7) - lsh[m];
-            lring[m] = slot * GS_S;
+            lring[m] = (slot - GS_SLOT0) * GS_S;
         }
         T *sdst[8];
         int sring[8];
@@ -172,7 +177,7 @@ __device__ __forceinline__ void gs_item(const GsJob<T> &A, int tau, int J, int K
             T *l0 = A.u + (int64_t)kg * A.plane + (int64_t)jg * A.px + h;
             ssh[m] = (int)((reinterpret_cast<uintptr_t>(l0) / sizeof(T)) & (GS_C - 1));
             sdst[m] = l0 + (e & 7) - ssh[m];
-            sring[m] = ((kq + 1) * 10 + (jq + 1)) * GS_S;
+            sring[m] = ((kq + 1) * 10 + (jq + 1) - GS_SLOT0) * GS_S;
         }
         // f (interior-only, its own row pitch) is staged with its own line
         // alignment: f chunk c covers [8c - fsh, 8c + 8 - fsh) of the line.
@@ -342,7 +347,7 @@ __device__ __forceinline__ void gs_item(const GsJob<T> &A, int tau, int J, int K
 
 template <typename T, bool HAS_A, bool HAS_F>
 __global__ void __launch_bounds__(64) gs_wavefront_kernel(GsArgs<T> G) {
-    __shared__ T ring[GS_SLOTS * GS_S];
+    __shared__ T ring[GS_RING_LEN];
     __shared__ T fring[HAS_F ? 78 * GS_S : 1];
     for (;;) {
         uint32_t t = 0;
@@ -358,7 +363,7 @@ __global__ void __launch_bounds__(64) gs_wavefront_kernel(GsArgs<T> G) {
 
 template <typename T, bool HAS_A, bool HAS_F>
 __global__ void __launch_bounds__(64) gs_batch_kernel(GsBatchArgs<T> G) {
-    __shared__ T ring[GS_SLOTS * GS_S];
+    __shared__ T ring[GS_RING_LEN];
     __shared__ T fring[HAS_F ? 78 * GS_S : 1];
     for (;;) {
         uint32_t t = 0;
