@@ -510,8 +510,8 @@ template <> struct CfgBase<double, 8> { static constexpr int VX = 1, RY = 5, NW 
 template <> struct CfgBase<float, 1> { static constexpr int VX = 2, RY = 8, NW = 8; };
 template <> struct CfgBase<float, 2> { static constexpr int VX = 2, RY = 8, NW = 8; };
 template <> struct CfgBase<float, 3> { static constexpr int VX = 2, RY = 8, NW = 8; };
-template <> struct CfgBase<float, 4> { static constexpr int VX = 2, RY = 6, NW = 8; };
-template <> struct CfgBase<float, 5> { static constexpr int VX = 1, RY = 8, NW = 8; };
+template <> struct CfgBase<float, 4> { static constexpr int VX = 1, RY = 12, NW = 8; };
+template <> struct CfgBase<float, 5> { static constexpr int VX = 1, RY = 12, NW = 8; };
 template <> struct CfgBase<float, 6> { static constexpr int VX = 1, RY = 8, NW = 8; };
 template <> struct CfgBase<float, 7> { static constexpr int VX = 1, RY = 8, NW = 8; };
 template <> struct CfgBase<float, 8> { static constexpr int VX = 1, RY = 8, NW = 8; };
@@ -528,8 +528,9 @@ template <> struct Cfg<double, 6, true> { static constexpr int VX = 1, RY = 5, N
 template <> struct Cfg<double, 7, true> { static constexpr int VX = 1, RY = 4, NW = 8; };
 template <> struct Cfg<double, 8, true> { static constexpr int VX = 1, RY = 4, NW = 8; };
 template <> struct Cfg<float, 3, true> { static constexpr int VX = 2, RY = 6, NW = 8; };
-template <> struct Cfg<float, 5, true> { static constexpr int VX = 1, RY = 6, NW = 8; };
-template <> struct Cfg<float, 6, true> { static constexpr int VX = 1, RY = 6, NW = 8; };
+template <> struct Cfg<float, 4, true> { static constexpr int VX = 2, RY = 6, NW = 8; };
+template <> struct Cfg<float, 5, true> { static constexpr int VX = 1, RY = 8, NW = 8; };
+template <> struct Cfg<float, 6, true> { static constexpr int VX = 1, RY = 8, NW = 8; };
 template <> struct Cfg<float, 7, true> { static constexpr int VX = 1, RY = 6, NW = 8; };
 template <> struct Cfg<float, 8, true> { static constexpr int VX = 1, RY = 6, NW = 8; };
 
