@@ -502,7 +502,7 @@ struct CfgBase;
 template <> struct CfgBase<double, 1> { static constexpr int VX = 2, RY = 4, NW = 8; };
 template <> struct CfgBase<double, 2> { static constexpr int VX = 2, RY = 4, NW = 8; };
 template <> struct CfgBase<double, 3> { static constexpr int VX = 1, RY = 10, NW = 8; };
-template <> struct CfgBase<double, 4> { static constexpr int VX = 1, RY = 8, NW = 8; };
+template <> struct CfgBase<double, 4> { static constexpr int VX = 1, RY = 9, NW = 8; };
 template <> struct CfgBase<double, 5> { static constexpr int VX = 1, RY = 7, NW = 8; };
 template <> struct CfgBase<double, 6> { static constexpr int VX = 1, RY = 6, NW = 8; };
 template <> struct CfgBase<double, 7> { static constexpr int VX = 1, RY = 5, NW = 8; };

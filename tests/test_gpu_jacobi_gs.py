@@ -60,7 +60,7 @@ JAC_CASES = [
     (17, 63, 65, 1, 5),
     (130, 33, 7, 1, 9),
     (257, 5, 9, 2, 6),
-    (119, 24, 40, 1, 8),    # one FP64 t=4 tile exactly
+    (119, 24, 40, 1, 8),    # x: two FP64 t=4 tiles of 56 and a ragged 7
     (245, 50, 19, 1, 13),
     (300, 70, 33, 1, 17),   # several tiles in x and y, several z-chunks
 ]
