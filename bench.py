@@ -92,6 +92,8 @@ def parse():
     ap.add_argument("--poisson-n", type=int, default=256)
     ap.add_argument("--poisson-m", type=int, default=32, help="inner sweeps per outer round")
     ap.add_argument("--poisson-methods", default="jacobi,gs,rbgs")
+    ap.add_argument("--poisson-inner", default="fp32_refined,plain_fp64",
+                    help="which solves of the Poisson comparison to run")
     ap.add_argument("--serving-jobs", type=int, default=300)
     ap.add_argument("--serving-rate", default="200",
                     help="arrival rate(s) per second, comma separated")
@@ -252,7 +254,8 @@ def small_grids(P, torch):
     return out
 
 
-def poisson_compare(P, torch, n, seed=0, methods=(0, 1, 2), m=32, tol=1e-10, chunk_s=30.0):
+def poisson_compare(P, torch, n, seed=0, methods=(0, 1, 2), m=32, tol=1e-10, chunk_s=30.0,
+                    inners=("fp32_refined", "plain_fp64")):
     """-Laplace u = f on n^3, h = 1/(n+1), f U[-1,1), u0 = 0: time to reach
     ||f' - A u|| <= tol ||f'|| with the FP32-refined loop and the plain FP64
     method.  The solve runs as consecutive library calls of a bounded number
@@ -267,6 +270,8 @@ def poisson_compare(P, torch, n, seed=0, methods=(0, 1, 2), m=32, tol=1e-10, chu
         name = ("jacobi", "gauss_seidel", "red_black")[method]
         res = {}
         for inner_fp32, key in ((True, "fp32_refined"), (False, "plain_fp64")):
+            if key not in inners:
+                continue
             u = torch.from_numpy(w["u"]).to("cuda")
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -293,12 +298,15 @@ def poisson_compare(P, torch, n, seed=0, methods=(0, 1, 2), m=32, tol=1e-10, chu
                         "MLUPs": round(float(n) ** 3 * sweeps / dt / 1e6)}
             res[key + "_u"] = u
             log("poisson %d^3 %s %s: %s" % (n, name, key, {k: v for k, v in res[key].items()}))
-        a, b = res.pop("fp32_refined_u"), res.pop("plain_fp64_u")
-        res["rel_diff_fp32_refined_vs_fp64"] = float((a - b).abs().max() / b.abs().max())
-        res["speedup_fp32_refined"] = round(res["plain_fp64"]["seconds"] /
-                                            res["fp32_refined"]["seconds"], 3)
+        if "fp32_refined_u" in res and "plain_fp64_u" in res:
+            a, b = res.pop("fp32_refined_u"), res.pop("plain_fp64_u")
+            res["rel_diff_fp32_refined_vs_fp64"] = float((a - b).abs().max() / b.abs().max())
+            res["speedup_fp32_refined"] = round(res["plain_fp64"]["seconds"] /
+                                                res["fp32_refined"]["seconds"], 3)
+            del a, b
+        for k in [k for k in res if k.endswith("_u")]:
+            del res[k]
         out[name] = res
-        del a, b
     return out
 
 
@@ -487,8 +495,9 @@ def main():
     if "poisson" in sections and args.poisson_n > 0:
         names = {"jacobi": 0, "gs": 1, "rbgs": 2}
         methods = tuple(names[x] for x in args.poisson_methods.split(","))
-        extra["poisson_%d" % args.poisson_n] = poisson_compare(P, torch, args.poisson_n,
-                                                               methods=methods, m=args.poisson_m)
+        extra["poisson_%d" % args.poisson_n] = poisson_compare(
+            P, torch, args.poisson_n, methods=methods, m=args.poisson_m,
+            inners=tuple(args.poisson_inner.split(",")))
 
     if "poisson" in sections:
         # the sizes the CPU oracle solves too (cpu_oracle_poisson_small)
