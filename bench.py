@@ -45,12 +45,18 @@ def eq1_mlups(bandwidth_GBs: float, elem_bytes: int = 8, t: int = 1) -> float:
 
 
 def jacobi_source_sha(t):
-    """Hash of the fused-pass kernel source as built for depth t."""
+    """Hash of the fused-pass kernel source as built for depth t, with
+    comments and blank lines removed (a comment edit does not change the
+    kernel the counters describe)."""
     import hashlib
+    import re
     cs = os.path.join(ROOT, "paper_1004_1741_amd", "csrc")
     h = hashlib.sha256()
     for name in ("jacobi_impl.h", "jacobi_t%d.hip" % t):
-        h.update(open(os.path.join(cs, name), "rb").read())
+        src = open(os.path.join(cs, name)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        lines = [re.sub(r"//.*$", "", ln).rstrip() for ln in src.split("\n")]
+        h.update("\n".join(ln for ln in lines if ln.strip()).encode())
     return h.hexdigest()[:16]
 
 

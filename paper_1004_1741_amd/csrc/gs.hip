@@ -28,12 +28,14 @@
 //     ever waits on items already held by running waves (no deadlock, no
 //     co-residency requirement).  Instead of barriers, a wave publishes a
 //     progress counter (chunks stored) per (sweep, bundle) after storing each
-//     chunk and polls its neighbours' counters before loading one
-//     (acquire/release at agent scope, across XCDs).  Counters are per sweep
-//     because several sweeps of one bundle are in flight at once;
-//   * all sweeps of a launch are in flight at once: sweep tau+1 of a bundle
-//     trails sweep tau by a few chunks, so the intermediate sweeps of a band
-//     of the grid are re-read from L2/MALL instead of HBM.
+//     chunk and polls its neighbours' counters before loading one (grid
+//     data and counters are device-scope relaxed atomics, coherent across
+//     XCDs; a chunk is published only after its stores have completed).
+//     Counters are per sweep because several sweeps of one bundle are in
+//     flight at once;
+//   * all sweeps of a launch are in flight at once: there is no launch
+//     boundary between sweeps, only the counters order sweep tau+1 of a
+//     bundle after sweep tau of it and of its neighbours.
 #include <algorithm>
 #include <map>
 #include <mutex>

@@ -8,13 +8,14 @@
 // barrier after every plane.  Here one workgroup owns an x-y tile of the grid
 // and marches it through z; the TB time levels of the tile live on chip:
 //
-//   * a wave covers 64*VX consecutive x sites (16-byte vector loads) and RY
-//     rows; NW waves stack in y, so a tile is (64*VX) x (NW*RY) sites;
+//   * a wave covers 64*VX consecutive x sites (one 16-byte load per row when
+//     VX*sizeof(T) == 16) and RY rows; NW waves stack in y, so a tile is
+//     (64*VX) x (NW*RY) sites;
 //   * level tau of plane p needs level tau-1 at planes p-1, p, p+1.  With a
 //     skew of one plane per level, step s loads plane s of level 0 and
-//     produces plane s-tau of level tau; the z-1 neighbour stays in a
-//     register ("prev") and the in-plane part of the sum is formed one step
-//     early ("q"), so each level keeps two planes in registers;
+//     produces plane s-tau of level tau.  Each level keeps its two newest
+//     planes in registers (centre plane and z-1 neighbour); the plane the
+//     level below produces in the same step supplies z+;
 //   * x neighbours come from adjacent lanes through DPP wave shifts, y
 //     neighbours from the thread's own rows or, at wave edges, through a
 //     small double-buffered LDS exchange (one barrier per step for all
@@ -24,6 +25,8 @@
 //     ghost cells inside a tile keep their Dirichlet value at every level;
 //   * z is split into chunks; a chunk starts TB planes early to fill the
 //     pipeline (or at the ghost plane, where all levels are known).
+//
+// The same pass runs red-black Gauss-Seidel (RB = true): see jacobi_tile.
 //
 // HBM sees one load of level 0 and one store of level TB per site per pass:
 // 2*sizeof(T) bytes per site per TB sweeps (Eq. (1) with the traffic divided
