@@ -37,6 +37,7 @@
 //     boundary between sweeps, only the counters order sweep tau+1 of a
 //     bundle after sweep tau of it and of its neighbours.
 #include <algorithm>
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -475,16 +476,17 @@ GsJob<T> make_job(const Geom &g, void *u, const void *f, double a, double b, dou
 }
 
 int device_cus(int dev) {
-    static int cached[64] = {0};
+    // cached on first use; concurrent first calls store the same value
+    static std::atomic<int> cached[64];
     if (dev < 0 || dev >= 64) return 256;
-    if (cached[dev] == 0) {
-        int ncu = 0;
+    int ncu = cached[dev].load(std::memory_order_relaxed);
+    if (ncu == 0) {
         if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) !=
                 hipSuccess || ncu < 1)
             ncu = 256;
-        cached[dev] = ncu;
+        cached[dev].store(ncu, std::memory_order_relaxed);
     }
-    return cached[dev];
+    return ncu;
 }
 
 template <typename K>
@@ -523,8 +525,12 @@ hipError_t launch_gs_t(const Geom &g, void *u, const void *f, double a, double b
     }
     hipLaunchKernelGGL(gs_reset_kernel, dim3(256), dim3(256), 0, s, G.job.progress, S * nj * nk,
                        G.ticket);
-    static int per_cu = 0;
-    if (per_cu == 0) per_cu = per_cu_occupancy(gs_wavefront_kernel<T, HAS_A, HAS_F>);
+    static std::atomic<int> per_cu_cached{0};
+    int per_cu = per_cu_cached.load(std::memory_order_relaxed);
+    if (per_cu == 0) {
+        per_cu = per_cu_occupancy(gs_wavefront_kernel<T, HAS_A, HAS_F>);
+        per_cu_cached.store(per_cu, std::memory_order_relaxed);
+    }
     int grid = per_cu * device_cus(dev);
     if ((uint32_t)grid > G.nitems) grid = (int)G.nitems;
     hipLaunchKernelGGL((gs_wavefront_kernel<T, HAS_A, HAS_F>), dim3(grid), dim3(64), 0, s, G);
@@ -617,8 +623,12 @@ hipError_t launch_gs_batch_t(const std::vector<GsBatchItem> &items, GsBatchWork 
     G.nitems = (uint32_t)w.items.size();
     G.items = ditems;
     G.ticket = dticket;
-    static int per_cu = 0;
-    if (per_cu == 0) per_cu = per_cu_occupancy(gs_batch_kernel<T, HAS_A, HAS_F>);
+    static std::atomic<int> per_cu_cached{0};
+    int per_cu = per_cu_cached.load(std::memory_order_relaxed);
+    if (per_cu == 0) {
+        per_cu = per_cu_occupancy(gs_batch_kernel<T, HAS_A, HAS_F>);
+        per_cu_cached.store(per_cu, std::memory_order_relaxed);
+    }
     int grid = per_cu * device_cus(dev);
     if ((uint32_t)grid > G.nitems) grid = (int)G.nitems;
     hipLaunchKernelGGL((gs_batch_kernel<T, HAS_A, HAS_F>), dim3(grid), dim3(64), 0, s, G);

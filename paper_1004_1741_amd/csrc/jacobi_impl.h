@@ -35,6 +35,7 @@
 // without FMA contraction, so every TB gives results bit-identical to TB
 // sequential sweeps.
 #pragma once
+#include <atomic>
 #include <type_traits>
 
 #include "internal.h"
@@ -566,10 +567,13 @@ int choose_chunks(const JacTileCfg &c, const Geom &g, int tiles_xy, int resident
 template <typename T, int TB, bool HAS_A, bool HAS_F, bool RB = false>
 int resident_wgs(bool batch) {
     using C = Cfg<T, TB, HAS_F>;
-    static int cached[2] = {0, 0};
-    int &r = cached[batch ? 1 : 0];
-    if (r == 0) {
-        int per_cu = 0, dev = 0, ncu = 0;
+    // Workgroups of this kernel per CU and CUs per device, cached on first use
+    // (concurrent first calls store the same values).
+    static std::atomic<int> per_cu_cached[2];
+    static std::atomic<int> ncu_cached[64];
+    std::atomic<int> &pc = per_cu_cached[batch ? 1 : 0];
+    int per_cu = pc.load(std::memory_order_relaxed);
+    if (per_cu == 0) {
         const void *kfn =
             batch ? reinterpret_cast<const void *>(
                         jacobi_batch_kernel<T, TB, C::VX, C::RY, C::NW, HAS_A, HAS_F>)
@@ -578,13 +582,18 @@ int resident_wgs(bool batch) {
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, C::NW * 64, 0) !=
                 hipSuccess || per_cu < 1)
             per_cu = 1;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) !=
+        pc.store(per_cu, std::memory_order_relaxed);
+    }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return per_cu * 256;
+    int ncu = ncu_cached[dev].load(std::memory_order_relaxed);
+    if (ncu == 0) {
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) !=
                 hipSuccess || ncu < 1)
             ncu = 256;
-        r = per_cu * ncu;
+        ncu_cached[dev].store(ncu, std::memory_order_relaxed);
     }
-    return r;
+    return per_cu * ncu;
 }
 
 template <typename T, int TB, bool HAS_F>
