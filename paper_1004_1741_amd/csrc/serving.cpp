@@ -1,6 +1,6 @@
 // serving.cpp -- continuous-batching job service (smooth_* in stencil.h).
 //
-// Jobs are independent smoothing problems of uneven sizes.  Three threads:
+// Jobs are independent smoothing problems of uneven sizes.  Threads:
 //   * scheduler: admits queued jobs while their device footprint fits the
 //     pool (one hipMalloc of hbm_budget_bytes, first-fit sub-allocation) and
 //     fewer than max_inflight are resident, then runs *iterations*: every
