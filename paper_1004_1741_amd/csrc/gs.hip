@@ -59,6 +59,9 @@ constexpr int GS_SLOTS = 100; // 10 x 10 staged lines (corners unused)
 // so five workgroups fit the 160 KB of LDS of a CU instead of four.
 constexpr int GS_SLOT0 = 1;
 constexpr int GS_RING_LEN = (GS_SLOTS - 2 - GS_SLOT0) * GS_S + GS_RING;
+// Right-hand side ring: the bundle's 64 own lines only, slot jj * 8 + kk (with
+// stride 41 the 32 lanes of a half-wave then read 32 distinct banks).
+constexpr int GS_FRING_LEN = 63 * GS_S + GS_RING;
 
 template <typename T>
 struct GsJob {
@@ -135,7 +138,7 @@ __device__ __forceinline__ void gs_item(const GsJob<T> &A, int tau, int J, int K
     const int kk = lane & 7, jj = lane >> 3;  // kk fastest: conflict-free LDS
     const int d = jj + kk;                    // skew of this lane's line
     const int own = (kk + 1) * 10 + (jj + 1) - GS_SLOT0;  // ring slot of this lane's line
-    const int fown = kk * 10 + jj;
+    const int fown = jj * 8 + kk;
     const int h = A.h;
         const int j0 = h + 8 * J, k0 = h + 8 * K;
         const int j = j0 + jj, k = k0 + kk;
@@ -260,7 +263,7 @@ __device__ __forceinline__ void gs_item(const GsJob<T> &A, int tau, int J, int K
 #pragma unroll
                 for (int m = 0; m < 8; ++m) {
                     const int li = (lane + 64 * m) >> 3;
-                    fring[((li >> 3) * 10 + (li & 7)) * GS_S + ((q - fsh[m]) & (GS_RING - 1))] =
+                    fring[((li & 7) * 8 + (li >> 3)) * GS_S + ((q - fsh[m]) & (GS_RING - 1))] =
                         fpf[m];
                 }
             }
@@ -351,7 +354,7 @@ __device__ __forceinline__ void gs_item(const GsJob<T> &A, int tau, int J, int K
 template <typename T, bool HAS_A, bool HAS_F>
 __global__ void __launch_bounds__(64) gs_wavefront_kernel(GsArgs<T> G) {
     __shared__ T ring[GS_RING_LEN];
-    __shared__ T fring[HAS_F ? 78 * GS_S : 1];
+    __shared__ T fring[HAS_F ? GS_FRING_LEN : 1];
     for (;;) {
         uint32_t t = 0;
         if (threadIdx.x == 0)
@@ -367,7 +370,7 @@ __global__ void __launch_bounds__(64) gs_wavefront_kernel(GsArgs<T> G) {
 template <typename T, bool HAS_A, bool HAS_F>
 __global__ void __launch_bounds__(64) gs_batch_kernel(GsBatchArgs<T> G) {
     __shared__ T ring[GS_RING_LEN];
-    __shared__ T fring[HAS_F ? 78 * GS_S : 1];
+    __shared__ T fring[HAS_F ? GS_FRING_LEN : 1];
     for (;;) {
         uint32_t t = 0;
         if (threadIdx.x == 0)
