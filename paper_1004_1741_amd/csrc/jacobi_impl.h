@@ -526,7 +526,7 @@ template <> struct CfgBase<float, 8> { static constexpr int VX = 1, RY = 8, NW =
 template <typename T, int TB, bool HAS_F>
 struct Cfg : CfgBase<T, TB> {};
 template <> struct Cfg<double, 3, true> { static constexpr int VX = 1, RY = 6, NW = 8; };
-template <> struct Cfg<double, 4, true> { static constexpr int VX = 1, RY = 6, NW = 8; };
+template <> struct Cfg<double, 4, true> { static constexpr int VX = 1, RY = 7, NW = 8; };
 template <> struct Cfg<double, 5, true> { static constexpr int VX = 1, RY = 5, NW = 8; };
 template <> struct Cfg<double, 6, true> { static constexpr int VX = 1, RY = 5, NW = 8; };
 template <> struct Cfg<double, 7, true> { static constexpr int VX = 1, RY = 4, NW = 8; };
