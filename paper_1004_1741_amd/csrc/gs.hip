@@ -51,17 +51,25 @@ namespace {
 
 constexpr int GS_C = 8;       // positions per load/store chunk
 constexpr int GS_RING = 32;   // ring positions per staged line (4 chunks)
-constexpr int GS_S = 41;      // LDS stride per line: S = 9 (mod 16) makes the
-                              // 64 lanes' reads hit distinct banks
 constexpr int GS_SLOTS = 100; // 10 x 10 staged lines (corners unused)
-// The ring holds slots 1..98 only (slots 0 and 99 are unused corners) and the
-// last one needs no stride padding: 97 * 41 + 32 values, 32072 bytes in FP64,
-// so five workgroups fit the 160 KB of LDS of a CU instead of four.
-constexpr int GS_SLOT0 = 1;
-constexpr int GS_RING_LEN = (GS_SLOTS - 2 - GS_SLOT0) * GS_S + GS_RING;
-// Right-hand side ring: the bundle's 64 own lines only, slot jj * 8 + kk (with
-// stride 41 the 32 lanes of a half-wave then read 32 distinct banks).
-constexpr int GS_FRING_LEN = 63 * GS_S + GS_RING;
+constexpr int GS_SLOT0 = 1;   // first slot held in LDS (slot 0 is an unused corner)
+
+// LDS layout of the ring, per element type.  The ring holds slots 1..98 only
+// (slots 0 and 99 are unused corners) and the last one needs no stride
+// padding: 97 * S + 32 values.  The LDS footprint of a workgroup (one wave)
+// sets how many fit a CU.  FP64 is sensitive to that: with S = 33 the ring is
+// 25864 bytes and six workgroups fit the 160 KB of a CU (S = 41, which
+// spreads the lanes' reads over more banks, allowed five and measured 19.2 ms
+// against 16.4 ms for 384^3 x 50).  FP32 is limited by registers to eight
+// waves per CU either way and keeps S = 41 (10.1 ms against 10.2 ms).  The
+// right-hand-side ring holds the bundle's 64 own lines only, slot jj * 8 + kk.
+template <typename T>
+struct GsLds {
+    static constexpr int S = sizeof(T) == 8 ? 33 : 41;
+    static constexpr int RING_LEN = (GS_SLOTS - 2 - GS_SLOT0) * S + GS_RING;
+    static constexpr int FRING_LEN = 63 * S + GS_RING;
+    static_assert(S >= GS_RING, "a staged line needs GS_RING positions");
+};
 
 template <typename T>
 struct GsJob {
@@ -137,6 +145,7 @@ __device__ __forceinline__ void gs_item(const GsJob<T> &A, int tau, int J, int K
     const int lane = threadIdx.x;
     const int kk = lane & 7, jj = lane >> 3;  // kk fastest: conflict-free LDS
     const int d = jj + kk;                    // skew of this lane's line
+    constexpr int GS_S = GsLds<T>::S;  // LDS stride per staged line
     const int own = (kk + 1) * 10 + (jj + 1) - GS_SLOT0;  // ring slot of this lane's line
     const int fown = jj * 8 + kk;
     const int h = A.h;
@@ -353,8 +362,8 @@ __device__ __forceinline__ void gs_item(const GsJob<T> &A, int tau, int J, int K
 
 template <typename T, bool HAS_A, bool HAS_F>
 __global__ void __launch_bounds__(64) gs_wavefront_kernel(GsArgs<T> G) {
-    __shared__ T ring[GS_RING_LEN];
-    __shared__ T fring[HAS_F ? GS_FRING_LEN : 1];
+    __shared__ T ring[GsLds<T>::RING_LEN];
+    __shared__ T fring[HAS_F ? GsLds<T>::FRING_LEN : 1];
     for (;;) {
         uint32_t t = 0;
         if (threadIdx.x == 0)
@@ -369,8 +378,8 @@ __global__ void __launch_bounds__(64) gs_wavefront_kernel(GsArgs<T> G) {
 
 template <typename T, bool HAS_A, bool HAS_F>
 __global__ void __launch_bounds__(64) gs_batch_kernel(GsBatchArgs<T> G) {
-    __shared__ T ring[GS_RING_LEN];
-    __shared__ T fring[HAS_F ? GS_FRING_LEN : 1];
+    __shared__ T ring[GsLds<T>::RING_LEN];
+    __shared__ T fring[HAS_F ? GsLds<T>::FRING_LEN : 1];
     for (;;) {
         uint32_t t = 0;
         if (threadIdx.x == 0)
