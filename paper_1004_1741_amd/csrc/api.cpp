@@ -120,12 +120,12 @@ int run_jacobi(const Geom &g, bool fp32, void *u, void *scratch, const void *f, 
     return ST_OK;
 }
 
-// Red-black sweeps per pass: at most 4 (8 levels on chip).  Automatic: 3
-// (6 levels; FP64 512^3 x 100 on MI355X: t=1 50.0 ms, 2: 31.4, 3: 30.5,
-// 4: 41.2), except FP64 with a right-hand side, where only 4 levels keep the
-// f ring in LDS (as for Jacobi with f, whose best depth is 4): 2.
+// Red-black sweeps per pass: at most 4 (8 levels on chip).  Automatic: FP64
+// 2 (4 levels; 512^3 x 100 on MI355X: t=1 50.6 ms, 2: 29.2, 3: 30.5, 4: 41.0;
+// with a right-hand side only 4 levels keep the f ring in LDS), FP32 3.
 int rb_sweeps_per_pass(int t_fuse, bool fp32, bool rhs) {
-    int t = t_fuse == 0 ? ((!fp32 && rhs) ? 2 : 3) : t_fuse;
+    (void)rhs;
+    int t = t_fuse == 0 ? (fp32 ? 3 : 2) : t_fuse;
     return t > 4 ? 4 : t;
 }
 
