@@ -76,7 +76,10 @@ typedef enum { ST_FP64 = 0, ST_FP32 = 1 } st_dtype;
 
 typedef enum { ST_BC_KEEP = 0, ST_BC_CONST = 1 } st_bc;
 
-/* Interior extents (>= 1) and ghost width (>= 1). */
+/* Interior extents (>= 1) and ghost width (1..4096).  One padded plane,
+ * (nx + 2*halo) * (ny + 2*halo) elements, must span < 2^31 bytes at 8 bytes
+ * per element (< 2^28 elements): kernels address a plane with 32-bit byte
+ * offsets.  Larger grids are ST_EINVAL. */
 typedef struct {
     int64_t nx, ny, nz;
     int32_t halo;

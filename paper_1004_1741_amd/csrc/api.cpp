@@ -47,9 +47,9 @@ int check_grid(const st_grid *g, Geom *out) {
     if (g->halo < 1) return fail(ST_EINVAL, "halo must be >= 1");
     const int64_t px = g->nx + 2 * (int64_t)g->halo, py = g->ny + 2 * (int64_t)g->halo,
                   pz = g->nz + 2 * (int64_t)g->halo;
-    // kernels index within a plane with 32-bit arithmetic
-    if (px * py >= (int64_t)1 << 31 || pz >= (int64_t)1 << 31 || g->halo > 4096)
-        return fail(ST_EINVAL, "grid too large (one padded plane must hold < 2^31 elements)");
+    // kernels address a plane with 32-bit byte offsets (8-byte elements)
+    if (px * py >= (int64_t)1 << 28 || pz >= (int64_t)1 << 31 || g->halo > 4096)
+        return fail(ST_EINVAL, "grid too large (one padded plane must hold < 2^28 elements)");
     out->nx = (int)g->nx;
     out->ny = (int)g->ny;
     out->nz = (int)g->nz;

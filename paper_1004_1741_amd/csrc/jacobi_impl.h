@@ -89,6 +89,8 @@ struct JacArgs {
     int tiles_x, tiles_y, nchunks, zc, ow, oh, ntiles;
 };
 
+typedef unsigned U32x2 __attribute__((ext_vector_type(2)));
+
 template <typename T, int VX, bool EDGE>
 __device__ __forceinline__ void load_row(const T *__restrict__ p, unsigned okmask, T (&out)[VX]) {
     if constexpr (!EDGE && (VX * sizeof(T) == 16 || (VX == 2 && sizeof(T) == 4))) {
@@ -401,7 +403,29 @@ __device__ __forceinline__ void jacobi_tile(const JacArgs<T> &A, int tx, int ty,
         }
         // store level TB of plane s-TB
         const int p = s - TB;
-        if (p >= z0 && p < z1) {
+        if constexpr (VX == 1) {
+            // One buffer store per row, issued on every step: lanes that must
+            // not write get an offset past the plane, which the buffer unit
+            // drops.  Stores issued unconditionally let the wait for the next
+            // plane's loads (the memory counter retires in issue order) leave
+            // this step's stores in flight; behind a branch the count would
+            // have to assume no store was issued and wait for them as well.
+            const bool pin = p >= z0 && p < z1;
+            const int nrec = (int)(A.plane * (int64_t)sizeof(T));
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                A.dst + (int64_t)(pin ? p : z0) * A.plane, 0, nrec, 0x00020000);
+#pragma unroll
+            for (int r = 0; r < RY; ++r) {
+                const bool ok = pin && (sty >> r & 1u) && (stx & 1u);
+                const int off = ok ? rowoff[r] * (int)sizeof(T) : nrec;
+                if constexpr (sizeof(T) == 8)
+                    __builtin_amdgcn_raw_buffer_store_b64(
+                        __builtin_bit_cast(U32x2, Nprev[r][0]), rs, off, 0, 0);
+                else
+                    __builtin_amdgcn_raw_buffer_store_b32(
+                        __builtin_bit_cast(unsigned, Nprev[r][0]), rs, off, 0, 0);
+            }
+        } else if (p >= z0 && p < z1) {
             T *base = A.dst + (int64_t)p * A.plane;
 #pragma unroll
             for (int r = 0; r < RY; ++r)
@@ -412,6 +436,10 @@ __device__ __forceinline__ void jacobi_tile(const JacArgs<T> &A, int tx, int ty,
     };
 
     using Part = std::integral_constant<bool, false>;
+    // Drain the prologue's loads here (vmcnt(0); expcnt and lgkmcnt left at
+    // their maxima): otherwise the loop header has to assume them pending and
+    // waits for every outstanding store on each iteration.
+    __builtin_amdgcn_s_waitcnt(0x0F70);
     int s = zb + 1;
     for (; s + 1 <= s_end; s += 2) {
         step(s, P0, P1, F0, F1, Part{});

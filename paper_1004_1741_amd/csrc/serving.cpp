@@ -483,8 +483,8 @@ int smooth_submit(smooth_ctx *c, const smooth_job *job, uint64_t *job_id) {
     if (!job->input_host || !job->output_host)
         return fail(ST_EINVAL, "input_host and output_host must not be NULL");
     const int64_t px = job->nx + 2, py = job->ny + 2, pz = job->nz + 2;
-    if (px * py >= ((int64_t)1 << 31) || pz >= ((int64_t)1 << 31))
-        return fail(ST_EINVAL, "grid too large");
+    if (px * py >= ((int64_t)1 << 28) || pz >= ((int64_t)1 << 31))
+        return fail(ST_EINVAL, "grid too large (one padded plane must hold < 2^28 elements)");
     if (job->method == SMOOTH_GS && (job->ny > 8192 || job->nz > 8192))
         return fail(ST_EINVAL, "Gauss-Seidel supports ny, nz <= 8192");
     std::unique_ptr<Job> j(new Job());
