@@ -155,6 +155,11 @@ __device__ __forceinline__ void jacobi_tile(const JacArgs<T> &A, int tx, int ty,
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const int h = A.h;
+    // Row stores as unconditional buffer stores (see the store at the end of
+    // a step) where one point per lane is stored.  The FP64 depth-4 tile with
+    // a right-hand side already sits at the register limit, and the store
+    // offsets make it spill (measured slower), so it keeps plain stores.
+    constexpr bool BUF_STORE = VX == 1 && !(sizeof(T) == 8 && TB == 4 && HAS_F);
 
     // ---- tile geometry (padded coordinates) ----
     const int ox0 = h + tx * A.ow;
@@ -403,7 +408,7 @@ __device__ __forceinline__ void jacobi_tile(const JacArgs<T> &A, int tx, int ty,
         }
         // store level TB of plane s-TB
         const int p = s - TB;
-        if constexpr (VX == 1) {
+        if constexpr (BUF_STORE) {
             // One buffer store per row, issued on every step: lanes that must
             // not write get an offset past the plane, which the buffer unit
             // drops.  Stores issued unconditionally let the wait for the next
