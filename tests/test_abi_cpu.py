@@ -68,6 +68,21 @@ def test_jacobi_validation(P, kw, status):
     assert L.stencil_last_error()
 
 
+@pytest.mark.parametrize("nx,ny", [(16382, 16382), ((1 << 26) - 2, 2), (2, (1 << 27) - 2)])
+def test_plane_size_limit(P, nx, ny):
+    """A padded plane of 2^28 or more elements is rejected before any device
+    call (kernels address a plane with 32-bit byte offsets)."""
+    L = P.lib()
+    g = P.Grid(nx, ny, 4, 1)
+    w = ctypes.byref(P.Weights(0.0, 1.0 / 6.0, 0.0))
+    for fn in (L.stencil_jacobi, L.stencil_rbgs):
+        rc = fn(ctypes.byref(g), 0, FAKE, FAKE2, None, w, 0, 0.0, 1, 0, None)
+        assert rc == P.ST.EINVAL
+        assert b"2^28" in L.stencil_last_error()
+    rc = L.stencil_gs(ctypes.byref(g), 0, FAKE, None, w, 0, 0.0, 1, 0, None)
+    assert rc == P.ST.EINVAL
+
+
 @pytest.mark.parametrize("kw,status", [
     (dict(nx=0), -1), (dict(dtype=7), -1), (dict(u=None), -1), (dict(scratch=None), -1),
     (dict(t=5), -1), (dict(t=-1), -1), (dict(sweeps=-1), -1), (dict(bc=9), -1),
