@@ -195,6 +195,20 @@ def test_jacobi_512_sampled(P, olib, t):
     assert got.min() >= 0.0 and got.max() < 1.0
 
 
+@pytest.mark.parametrize("t", [4, 5])
+def test_jacobi_512_full_two_passes(P, olib, t):
+    """The whole 512^3 grid after two passes of depth t, element by element:
+    every tile overlap and z-chunk seam of the benchmark's launch shape."""
+    w = si.jacobi_512(seed=0)
+    u = w["u"]
+    S = 2 * t
+    say("jacobi 512^3 x%d t=%d, whole grid (GPU)" % (S, t))
+    got = _run_jacobi(P, u, S, t)
+    say("  oracle 512^3 x%d" % S)
+    ref = oracle.jacobi(u, S, lib=olib)
+    assert_same(got, ref, "512^3 x%d t=%d whole grid" % (S, t))
+
+
 # --- Gauss-Seidel ---------------------------------------------------------------
 
 GS_CASES = [
