@@ -57,15 +57,18 @@ constexpr int GS_SLOT0 = 1;   // first slot held in LDS (slot 0 is an unused cor
 // LDS layout of the ring, per element type.  The ring holds slots 1..98 only
 // (slots 0 and 99 are unused corners) and the last one needs no stride
 // padding: 97 * S + 32 values.  The LDS footprint of a workgroup (one wave)
-// sets how many fit a CU.  FP64 is sensitive to that: with S = 33 the ring is
-// 25864 bytes and six workgroups fit the 160 KB of a CU (S = 41, which
-// spreads the lanes' reads over more banks, allowed five and measured 19.2 ms
-// against 16.4 ms for 384^3 x 50).  FP32 is limited by registers to eight
-// waves per CU either way and keeps S = 41 (10.1 ms against 10.2 ms).  The
-// right-hand-side ring holds the bundle's 64 own lines only, slot jj * 8 + kk.
+// sets how many fit a CU.  FP64 is sensitive to that: S <= 34 keeps six
+// workgroups in the 160 KB of a CU (S = 41 allowed five: 19.2 ms against
+// 16.4 ms for 384^3 x 50).  Within that limit S = 34 spreads a wave's ring
+// reads best: lane (jj, kk) reads value (10 kk + jj + 10) S - jj - kk + const,
+// so with S = 33 the jj term vanishes modulo the 32 bank pairs and eight lanes
+// share a bank pair; with S = 34 four do.  FP32 is limited by registers to
+// eight waves per CU either way and keeps S = 41 (one lane per bank; 10.1 ms
+// against 10.2 ms).  The right-hand-side ring holds the bundle's 64 own lines
+// only, slot jj * 8 + kk.
 template <typename T>
 struct GsLds {
-    static constexpr int S = sizeof(T) == 8 ? 33 : 41;
+    static constexpr int S = sizeof(T) == 8 ? 34 : 41;
     static constexpr int RING_LEN = (GS_SLOTS - 2 - GS_SLOT0) * S + GS_RING;
     static constexpr int FRING_LEN = 63 * S + GS_RING;
     static_assert(S >= GS_RING, "a staged line needs GS_RING positions");
