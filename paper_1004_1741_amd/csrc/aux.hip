@@ -7,25 +7,43 @@
 namespace stk {
 namespace {
 
-// One 64-lane wave per padded row (k, j).  Rows that lie entirely in the
-// ghost layer are processed whole; interior rows only touch their 2h ghosts.
+// Ghost layer of a padded grid in two parts.  Blocks [0, nfull) take the
+// rows that lie entirely in the ghost layer (z ghost planes, then the y ghost
+// rows of interior planes), one 64-lane wave per row.  The remaining blocks
+// take the 2h x ghosts of every interior row, one element per thread, so the
+// interior rows cost no idle waves.
 template <typename T, bool COPY>
 __global__ void __launch_bounds__(256) ghost_kernel(T *__restrict__ dst, const T *__restrict__ src,
                                                     T value, int64_t px, int64_t py, int64_t pz,
-                                                    int h) {
-    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (row >= py * pz) return;
-    const int lane = threadIdx.x & 63;
-    const int64_t k = row / py, j = row - k * py;
-    const bool ghost_row = k < h || k >= pz - h || j < h || j >= py - h;
-    const int64_t base = row * px;
-    if (ghost_row) {
-        for (int64_t i = lane; i < px; i += 64) dst[base + i] = COPY ? src[base + i] : value;
-    } else {
-        for (int i = lane; i < 2 * h; i += 64) {
-            const int64_t x = i < h ? i : px - 2 * h + i;
-            dst[base + x] = COPY ? src[base + x] : value;
+                                                    int h, int64_t nfull) {
+    const int64_t zrows = 2 * h * py;          // rows of the 2h ghost planes
+    const int64_t nyi = py - 2 * h, nzi = pz - 2 * h;
+    if ((int64_t)blockIdx.x < nfull) {
+        const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+        int64_t k, j;
+        if (r < zrows) {
+            const int64_t pl = r / py;                   // 0 .. 2h-1
+            k = pl < h ? pl : pz - 2 * h + pl;
+            j = r - pl * py;
+        } else {
+            const int64_t q = r - zrows;                 // y ghost rows of interior planes
+            if (q >= 2 * h * nzi) return;
+            const int64_t kk = q / (2 * h), jj = q - kk * (2 * h);
+            k = h + kk;
+            j = jj < h ? jj : py - 2 * h + jj;
         }
+        const int64_t base = (k * py + j) * px;
+        for (int64_t i = threadIdx.x & 63; i < px; i += 64)
+            dst[base + i] = COPY ? src[base + i] : value;
+    } else {
+        const int64_t e = ((int64_t)blockIdx.x - nfull) * 256 + threadIdx.x;
+        if (e >= nzi * nyi * 2 * h) return;
+        const int64_t row = e / (2 * h);
+        const int i = (int)(e - row * (2 * h));
+        const int64_t k = h + row / nyi, j = h + row % nyi;
+        const int64_t x = i < h ? i : px - 2 * h + i;
+        const int64_t o = (k * py + j) * px + x;
+        dst[o] = COPY ? src[o] : value;
     }
 }
 
@@ -139,28 +157,39 @@ int row_blocks(const Geom &g) { return g.nz * ((g.ny + 3) / 4); }
 
 }  // namespace
 
+namespace {
+struct GhostGrid {
+    dim3 grid;
+    int64_t nfull;
+};
+GhostGrid ghost_grid(const Geom &g) {
+    const int64_t full_rows = 2 * g.h * g.py + 2 * g.h * (g.pz - 2 * g.h);
+    const int64_t xg = (g.pz - 2 * g.h) * (g.py - 2 * g.h) * 2 * g.h;
+    const int64_t nfull = (full_rows + 3) / 4;
+    return GhostGrid{dim3((unsigned)(nfull + (xg + 255) / 256)), nfull};
+}
+}  // namespace
+
 hipError_t launch_fill_ghosts(bool fp32, const Geom &g, void *u, double value, hipStream_t s) {
-    const int64_t rows = g.py * g.pz;
-    const dim3 grid((unsigned)((rows + 3) / 4));
+    const GhostGrid q = ghost_grid(g);
     if (fp32)
-        hipLaunchKernelGGL((ghost_kernel<float, false>), grid, dim3(256), 0, s, (float *)u,
-                           (const float *)nullptr, (float)value, g.px, g.py, g.pz, g.h);
+        hipLaunchKernelGGL((ghost_kernel<float, false>), q.grid, dim3(256), 0, s, (float *)u,
+                           (const float *)nullptr, (float)value, g.px, g.py, g.pz, g.h, q.nfull);
     else
-        hipLaunchKernelGGL((ghost_kernel<double, false>), grid, dim3(256), 0, s, (double *)u,
-                           (const double *)nullptr, value, g.px, g.py, g.pz, g.h);
+        hipLaunchKernelGGL((ghost_kernel<double, false>), q.grid, dim3(256), 0, s, (double *)u,
+                           (const double *)nullptr, value, g.px, g.py, g.pz, g.h, q.nfull);
     return hipGetLastError();
 }
 
 hipError_t launch_copy_ghosts(bool fp32, const Geom &g, const void *src, void *dst,
                               hipStream_t s) {
-    const int64_t rows = g.py * g.pz;
-    const dim3 grid((unsigned)((rows + 3) / 4));
+    const GhostGrid q = ghost_grid(g);
     if (fp32)
-        hipLaunchKernelGGL((ghost_kernel<float, true>), grid, dim3(256), 0, s, (float *)dst,
-                           (const float *)src, 0.0f, g.px, g.py, g.pz, g.h);
+        hipLaunchKernelGGL((ghost_kernel<float, true>), q.grid, dim3(256), 0, s, (float *)dst,
+                           (const float *)src, 0.0f, g.px, g.py, g.pz, g.h, q.nfull);
     else
-        hipLaunchKernelGGL((ghost_kernel<double, true>), grid, dim3(256), 0, s, (double *)dst,
-                           (const double *)src, 0.0, g.px, g.py, g.pz, g.h);
+        hipLaunchKernelGGL((ghost_kernel<double, true>), q.grid, dim3(256), 0, s, (double *)dst,
+                           (const double *)src, 0.0, g.px, g.py, g.pz, g.h, q.nfull);
     return hipGetLastError();
 }
 
