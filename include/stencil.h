@@ -227,7 +227,8 @@ enum { SMOOTH_QUEUED = 0, SMOOTH_RUNNING = 1, SMOOTH_DONE = 2, SMOOTH_FAILED = 3
 
 /*
  * One smoothing job: `sweeps` sweeps of `method` on a grid of interior
- * extents nx, ny, nz with a ghost layer of width 1.
+ * extents nx, ny, nz with a ghost layer of width 1 (the st_grid limits apply:
+ * one padded plane < 2^28 elements; Gauss-Seidel also needs ny, nz <= 8192).
  *  precision SMOOTH_FP64: plain FP64 sweeps (bit-identical to stencil_jacobi
  *            / stencil_gs).  SMOOTH_FP32_REFINED: one defect-correction step,
  *            r = (one FP64 update of u0) - u0, `sweeps` float sweeps of
