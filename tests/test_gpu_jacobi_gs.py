@@ -93,6 +93,20 @@ def test_jacobi_zero_sweeps_and_bc(P, olib):
     assert_same(to_host(du), oracle.jacobi(exp, 3, lib=olib), "bc fill + 3 sweeps")
 
 
+@pytest.mark.parametrize("h", [2, 3])
+def test_ghost_fill_and_copy_wide_halo(P, olib, h):
+    """Ghost fill (BC_CONST) and the ghost copy into scratch with a halo wider
+    than one: whole ghost rows and the 2h x ghosts of interior rows."""
+    import paper_1004_1741_amd as PP
+    u = si.uniform_padded(37, 11, 6, h, seed=21)
+    du, ds = to_dev(u), to_dev(np.zeros_like(u))
+    PP.jacobi(du, ds, 0, bc=PP.ST.BC_CONST, bc_value=-0.5, halo=h)
+    exp = si.set_ghosts(u.copy(), h, -0.5)
+    assert_same(to_host(du), exp, "bc fill only, h=%d" % h)
+    PP.jacobi(du, ds, 5, t_fuse=1, halo=h)   # five one-sweep passes (odd count)
+    assert_same(to_host(du), oracle.jacobi(exp, 5, h=h, lib=olib), "5 sweeps, h=%d" % h)
+
+
 def test_jacobi_split_invariance(P, olib):
     u = si.uniform_padded(90, 40, 30, 1, seed=9)
     a = _run_jacobi(P, _run_jacobi(P, u, 7, 4), 6, 2)
