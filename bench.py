@@ -458,8 +458,12 @@ def main():
             jacobi_run(P, torch, u32, s32, S, t)
             m = events_time(torch, lambda: jacobi_run(P, torch, u32, s32, S, t), reps=2) / 2
             pl, _ = P.jacobi_plan(S, t, fp32=True)
+            pms = m / len(pl)
+            pb32 = pass_bytes / 2  # 4-byte elements: one load and one store per site
             per32[str(t)] = {"ms": round(m, 3), "MLUPs": round(lups_step / (m * 1e-3) / 1e6),
-                             "passes": len(pl)}
+                             "passes": len(pl), "pass_us": round(pms * 1e3, 1),
+                             "pass_GBs": round(pb32 / (pms * 1e-3) / 1e9, 1),
+                             "pass_frac": round(pb32 / (pms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
             log("jacobi fp32 t=%d: %s" % (t, per32[str(t)]))
         extra["jacobi_fp32_by_t"] = per32
         del u32, s32
