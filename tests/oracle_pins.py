@@ -294,82 +294,114 @@ def pin_split_invariance(lib):
         assert np.array_equal(fn(u, 0, lib=lib), u)
 
 
-# ------------------------------------------------- printed loop nests -----
+# -------------------------------------------- operand order, both dtypes -----
+# The update rule as the library header states it (and as Sec. 3 defines the
+# sweep): s = ((((x- + x+) + y-) + y+) + z-) + z+, v = (a*c) + (b*s), then
+# v + (g*f).  The two references below evaluate exactly that rule in IEEE
+# arithmetic of the requested dtype (numpy float64 / float32 arrays and
+# scalars), independently of the oracle's loop nests: Jacobi as whole-array
+# slices, Gauss-Seidel as one sequential loop over flat interior indices.
 
-def _listing_jacobi(u, S, a, b):
-    """Brute-force transcription of the Sec. 3 Jacobi loop nest (pure Python floats)."""
-    src = u.tolist()
-    nz, ny, nx = len(src) - 2, len(src[0]) - 2, len(src[0][0]) - 2
+def _rule(dt, c, xm, xp, ym, yp, zm, zp, a, b, g, fv):
+    s = xm + xp
+    s = s + ym
+    s = s + yp
+    s = s + zm
+    s = s + zp
+    v = (dt(a) * c) + (dt(b) * s) if a != 0.0 else dt(b) * s
+    if fv is not None:
+        v = v + (dt(g) * fv)
+    return v
+
+
+def _slices_jacobi(u, S, a, b, f=None, g=0.0, h=1):
+    """Two-array Jacobi sweeps with numpy slices in the dtype of u."""
+    dt = u.dtype.type
+    cur = u.copy()
+    nz, ny, nx = (d - 2 * h for d in u.shape)
+    I = (slice(h, h + nz), slice(h, h + ny), slice(h, h + nx))
     for _ in range(S):
-        dst = [[row[:] for row in plane] for plane in src]
-        for k in range(1, nz + 1):
-            for j in range(1, ny + 1):
-                for i in range(1, nx + 1):
-                    v = b * (src[k][j][i - 1] + src[k][j][i + 1] + src[k][j - 1][i]
-                             + src[k][j + 1][i] + src[k - 1][j][i] + src[k + 1][j][i])
-                    if a != 0.0:
-                        v = a * src[k][j][i] + v
-                    dst[k][j][i] = v
-        src = dst
-    return np.array(src)
+        nxt = cur.copy()
+        nxt[I] = _rule(dt, cur[I],
+                       cur[h:h + nz, h:h + ny, h - 1:h + nx - 1], cur[h:h + nz, h:h + ny, h + 1:h + nx + 1],
+                       cur[h:h + nz, h - 1:h + ny - 1, h:h + nx], cur[h:h + nz, h + 1:h + ny + 1, h:h + nx],
+                       cur[h - 1:h + nz - 1, h:h + ny, h:h + nx], cur[h + 1:h + nz + 1, h:h + ny, h:h + nx],
+                       a, b, g, f)
+        cur = nxt
+    return cur
 
 
-def _listing_gs(u, S, b):
-    """Brute-force transcription of the Sec. 3 Gauss-Seidel loop nest."""
-    src = u.tolist()
-    nz, ny, nx = len(src) - 2, len(src[0]) - 2, len(src[0][0]) - 2
+def _flat_gs(u, S, a, b, f=None, g=0.0, h=1):
+    """In-place Gauss-Seidel as one sequential loop over the flat interior
+    indices in increasing order (numpy scalars of the dtype of u)."""
+    dt = u.dtype.type
+    pz, py, px = u.shape
+    plane = py * px
+    flat = u.copy().reshape(-1)
+    ff = None if f is None else f.reshape(-1)
     for _ in range(S):
-        for k in range(1, nz + 1):
-            for j in range(1, ny + 1):
-                for i in range(1, nx + 1):
-                    src[k][j][i] = b * (src[k][j][i - 1] + src[k][j][i + 1] + src[k][j - 1][i]
-                                        + src[k][j + 1][i] + src[k - 1][j][i] + src[k + 1][j][i])
-    return np.array(src)
+        q = 0
+        for k in range(h, pz - h):
+            for j in range(h, py - h):
+                for i in range(h, px - h):
+                    o = (k * py + j) * px + i
+                    flat[o] = _rule(dt, flat[o], flat[o - 1], flat[o + 1], flat[o - px],
+                                    flat[o + px], flat[o - plane], flat[o + plane], a, b, g,
+                                    None if ff is None else ff[q])
+                    q += 1
+    return flat.reshape(u.shape)
 
 
-def pin_listing_order(lib):
-    """Operand order of the printed loop nests (C left association), bit-exact."""
+def pin_operand_order(lib):
+    """Bit-exact against the stated update rule, FP64 and float, with and
+    without the centre and right-hand-side terms: pins the summation order."""
     rng = np.random.default_rng(0)
-    u = np.zeros((10, 10, 10))
-    u[1:-1, 1:-1, 1:-1] = 2 * rng.random((8, 8, 8)) - 1
-    assert np.array_equal(oracle.gauss_seidel(u, 3, lib=lib), _listing_gs(u, 3, 1.0 / 6.0))
-    u = rng.random((7, 8, 9))
-    assert np.array_equal(oracle.jacobi(u, 4, lib=lib), _listing_jacobi(u, 4, 0.0, 1.0 / 6.0))
-    assert np.array_equal(oracle.jacobi(u, 2, a=0.3, b=0.1, lib=lib),
-                          _listing_jacobi(u, 2, 0.3, 0.1))
+    for dt in (np.float64, np.float32):
+        u = np.zeros((10, 10, 10), dtype=dt)
+        u[1:-1, 1:-1, 1:-1] = (2 * rng.random((8, 8, 8)) - 1).astype(dt)
+        f = (rng.random((8, 8, 8)) - 0.5).astype(dt)
+        for a, b, g, ff in ((0.0, 1.0 / 6.0, 0.0, None), (0.3, 0.1, 0.25, f)):
+            assert np.array_equal(oracle.gauss_seidel(u, 3, a=a, b=b, f=ff, g=g, lib=lib),
+                                  _flat_gs(u, 3, a, b, ff, g)), (dt, a)
+        v = rng.random((7, 8, 9)).astype(dt)
+        fv = (rng.random((5, 6, 7)) - 0.5).astype(dt)
+        for a, b, g, ff, S in ((0.0, 1.0 / 6.0, 0.0, None, 4), (0.3, 0.1, 0.0, None, 2),
+                               (0.0, 1.0 / 6.0, 1.0 / 6.0, fv, 3)):
+            assert np.array_equal(oracle.jacobi(v, S, a=a, b=b, f=ff, g=g, lib=lib),
+                                  _slices_jacobi(v, S, a, b, ff, g)), (dt, a, S)
 
 
 def pin_red_black_masks(lib):
     """Red-black = masked Jacobi on the red sites, then on the black sites with
-    the new red values (numpy slicing, same operand order: bit-exact), and it
-    differs from the lexicographic sweep."""
+    the new red values (numpy slicing in the grid's dtype, same operand order:
+    bit-exact, FP64 and float), and it differs from the lexicographic sweep."""
     rng = np.random.default_rng(5)
-    for h, (nx, ny, nz), a, b, use_f in ((1, (9, 6, 7), 0.0, 1.0 / 6.0, False),
-                                         (2, (5, 8, 4), 0.3, 0.11, True)):
-        u = rng.random((nz + 2 * h, ny + 2 * h, nx + 2 * h)) * 2 - 1
-        f = rng.random((nz, ny, nx)) - 0.5 if use_f else None
-        g = 0.25
-        kk, jj, ii = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
-        parity = (ii + jj + kk) % 2
-        ref = u.copy()
-        I = (slice(h, h + nz), slice(h, h + ny), slice(h, h + nx))
-        for _ in range(3):
-            for color in (0, 1):
-                c = ref[I]
-                s = ref[h:h + nz, h:h + ny, h - 1:h + nx - 1] + ref[h:h + nz, h:h + ny, h + 1:h + nx + 1]
-                s = s + ref[h:h + nz, h - 1:h + ny - 1, h:h + nx]
-                s = s + ref[h:h + nz, h + 1:h + ny + 1, h:h + nx]
-                s = s + ref[h - 1:h + nz - 1, h:h + ny, h:h + nx]
-                s = s + ref[h + 1:h + nz + 1, h:h + ny, h:h + nx]
-                v = (a * c) + (b * s) if a != 0.0 else b * s
-                if f is not None:
-                    v = v + (g * f)
-                ref[I] = np.where(parity == color, v, c)
-        out = oracle.red_black(u, 3, a=a, b=b, f=f, g=g, h=h, lib=lib)
-        assert np.array_equal(out, ref), (h, a)
-        assert not np.array_equal(out, oracle.gauss_seidel(u, 3, a=a, b=b, f=f, g=g, h=h, lib=lib))
+    for dt in (np.float64, np.float32):
+        for h, (nx, ny, nz), a, b, use_f in ((1, (9, 6, 7), 0.0, 1.0 / 6.0, False),
+                                             (2, (5, 8, 4), 0.3, 0.11, True)):
+            u = (rng.random((nz + 2 * h, ny + 2 * h, nx + 2 * h)) * 2 - 1).astype(dt)
+            f = (rng.random((nz, ny, nx)) - 0.5).astype(dt) if use_f else None
+            g = 0.25
+            kk, jj, ii = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+            parity = (ii + jj + kk) % 2
+            ref = u.copy()
+            I = (slice(h, h + nz), slice(h, h + ny), slice(h, h + nx))
+            for _ in range(3):
+                for color in (0, 1):
+                    v = _rule(dt, ref[I],
+                              ref[h:h + nz, h:h + ny, h - 1:h + nx - 1],
+                              ref[h:h + nz, h:h + ny, h + 1:h + nx + 1],
+                              ref[h:h + nz, h - 1:h + ny - 1, h:h + nx],
+                              ref[h:h + nz, h + 1:h + ny + 1, h:h + nx],
+                              ref[h - 1:h + nz - 1, h:h + ny, h:h + nx],
+                              ref[h + 1:h + nz + 1, h:h + ny, h:h + nx], a, b, g, f)
+                    ref[I] = np.where(parity == color, v, ref[I])
+            out = oracle.red_black(u, 3, a=a, b=b, f=f, g=g, h=h, lib=lib)
+            assert np.array_equal(out, ref), (dt, h, a)
+            assert not np.array_equal(out, oracle.gauss_seidel(u, 3, a=a, b=b, f=f, g=g, h=h,
+                                                               lib=lib))
 
 
-ALL_PINS = [pin_listing_order, pin_jacobi_sine_decay, pin_fixed_points, pin_exact_rational, pin_exact_rational_f32,
+ALL_PINS = [pin_operand_order, pin_jacobi_sine_decay, pin_fixed_points, pin_exact_rational, pin_exact_rational_f32,
             pin_gs_rate, pin_gs_differs_from_jacobi, pin_residual_mode, pin_defect_correction,
             pin_manufactured_solution, pin_split_invariance, pin_red_black_masks]

@@ -47,6 +47,22 @@ MUTATIONS = [
     ("refine_f32_no_correction", "oracle_refine",
      "u[IDX(k, j, i)] = u[IDX(k, j, i)] + (double)e32[IDX(k, j, i)];",
      "u[IDX(k, j, i)] = u[IDX(k, j, i)] + 0.5 * (double)e32[IDX(k, j, i)];"),
+    ("jacobi_f32_operand_order", "oracle_jacobi_f32",
+     "s = s + src[IDX(k, j - 1, i)];\n                    s = s + src[IDX(k, j + 1, i)];\n"
+     "                    s = s + src[IDX(k - 1, j, i)];",
+     "s = s + src[IDX(k - 1, j, i)];\n                    s = s + src[IDX(k, j + 1, i)];\n"
+     "                    s = s + src[IDX(k, j - 1, i)];"),
+    ("gs_f32_operand_order", "oracle_gs_f32",
+     "s = s + u[IDX(k, j + 1, i)];\n                    s = s + u[IDX(k - 1, j, i)];",
+     "s = s + u[IDX(k - 1, j, i)];\n                    s = s + u[IDX(k, j + 1, i)];"),
+    ("gs_f32_sum_in_double", "oracle_gs_f32",
+     "float s = u[IDX(k, j, i - 1)];", "double s = u[IDX(k, j, i - 1)];"),
+    ("rbgs_f32_operand_order", "oracle_rbgs_f32",
+     "s = s + u[IDX(k - 1, j, i)];\n                        s = s + u[IDX(k + 1, j, i)];",
+     "s = s + u[IDX(k + 1, j, i)];\n                        s = s + u[IDX(k - 1, j, i)];"),
+    ("jacobi_f32_update_in_double", "oracle_jacobi_f32",
+     "v = (a * src[IDX(k, j, i)]) + (b * s);",
+     "v = (float)(((double)a * src[IDX(k, j, i)]) + ((double)b * s));"),
 ]
 
 
