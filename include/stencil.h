@@ -126,18 +126,62 @@ int stencil_jacobi_plan(int32_t dtype, int32_t has_rhs, int32_t sweeps, int32_t 
                         int32_t *passes, int32_t *t_list, int32_t max_list, int32_t *final_copy);
 
 /*
+ * stencil_jacobi_tiles -- how one fused pass of `levels` time levels (1..8)
+ * tiles the x-y cross-section of a grid: stencil_jacobi runs t_fuse sweeps
+ * as t_fuse levels, stencil_rbgs one red-black sweep as two levels.  Writes
+ * the stored tile width and height (each tile also reads `levels` sites
+ * beyond them on every side: the dependency cone of Sec. 4's temporal
+ * blocking), the number of x-y tiles, and how many of them lie wholly inside
+ * the interior (those run without per-site boundary masks).  Host-only; any
+ * output pointer may be NULL.  ST_EINVAL for a bad grid, dtype or level count.
+ */
+int stencil_jacobi_tiles(const st_grid *grid, int32_t dtype, int32_t has_rhs, int32_t levels,
+                         int32_t *tile_w, int32_t *tile_h, int32_t *tiles, int32_t *interior);
+
+/*
  * stencil_gs -- `sweeps` in-place lexicographic Gauss-Seidel sweeps
  * (Sec. 3 loop nest), run as a pipelined wavefront: the pipeline-parallel
  * and temporal-wavefront schemes of Sec. 3/4 re-expressed as bundles of
  * x-lines scheduled in topological order with per-bundle progress counters
  * instead of barriers.  t_fuse sweeps are in flight per launch (0 = all
- * sweeps in one launch; 1 = one launch per sweep; 1..8 or 16 accepted).
- * Bit-identical to the sequential loop nest.  Uses an internal flag buffer
- * owned by the library.
+ * sweeps in one launch, at most 4095; 1 = one launch per sweep; 1..8 or 16
+ * accepted).  Bit-identical to the sequential loop nest.  Each launch takes
+ * its workspace (progress counters, ticket and item table, about 8 bytes per
+ * (sweep, 8x8 bundle of x-lines)) from the stream-ordered allocator
+ * (hipMallocAsync on hip_stream) and returns it after the launch; waits are
+ * bounded (see stencil_sync).
  * Same argument meanings as stencil_jacobi.
  */
 int stencil_gs(const st_grid *grid, int32_t dtype, void *u, const void *f, const st_weights *w,
                int32_t bc, double bc_value, int32_t sweeps, int32_t t_fuse, void *hip_stream);
+
+/*
+ * Bounded waits of the Gauss-Seidel wavefront.  A wave of the wavefront
+ * kernel waits (spins) on its neighbours' progress counters.  Every such
+ * wait is bounded: after `polls` polls (stencil_gs_spin_limit; default 2^24,
+ * a few seconds), or once the device's abort word is raised, the wave gives
+ * up, raises the abort word, and every wave of that and later launches on the
+ * device then finishes its remaining work without waiting and exits: a
+ * protocol fault ends the kernel instead of hanging the device.  The grid of
+ * a launch that gave up holds partial results.
+ *
+ * stencil_sync        -- synchronizes hip_stream, then returns ST_EHIP if a
+ *                        wavefront launch on the current device gave up since
+ *                        the last stencil_sync (else ST_OK), and clears the
+ *                        abort word and that status.  stencil_refine_solve
+ *                        checks the same status after every round that used
+ *                        the wavefront.
+ * stencil_gs_abort    -- raises the abort word of `device` from the host (on a
+ *                        stream of its own, so it lands while launches on
+ *                        other streams run); returns once it is written.
+ *                        ST_EINVAL for an unknown device.
+ * stencil_gs_spin_limit -- polls of one wait before giving up, process-wide
+ *                        (0 = default); ST_EINVAL outside 0..2^32-1.
+ * The status and the abort word are per device, shared by every stream.
+ */
+int stencil_sync(void *hip_stream);
+int stencil_gs_abort(int32_t device);
+int stencil_gs_spin_limit(int64_t polls);
 
 /*
  * stencil_rbgs -- `sweeps` red-black Gauss-Seidel sweeps: the alternative

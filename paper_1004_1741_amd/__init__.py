@@ -13,7 +13,8 @@ from __future__ import annotations
 import ctypes
 import pathlib
 
-__all__ = ["lib", "jacobi", "gauss_seidel", "red_black", "residual", "refine_solve", "jacobi_plan",
+__all__ = ["lib", "jacobi", "gauss_seidel", "red_black", "residual", "refine_solve", "jacobi_plan", "jacobi_tiles",
+           "sync", "gs_abort", "gs_spin_limit",
            "StencilError", "SmoothService", "ST", "LIB_PATH"]
 
 LIB_PATH = pathlib.Path(__file__).resolve().parent / "libstencil.so"
@@ -78,7 +79,12 @@ _vp, _i32, _i64, _dbl, _u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, c
 SIGNATURES = [
     ("stencil_jacobi", _i32, [_P(Grid), _i32, _vp, _vp, _vp, _P(Weights), _i32, _dbl, _i32, _i32, _vp]),
     ("stencil_jacobi_plan", _i32, [_i32, _i32, _i32, _i32, _P(_i32), _P(_i32), _i32, _P(_i32)]),
+    ("stencil_jacobi_tiles", _i32, [_P(Grid), _i32, _i32, _i32, _P(_i32), _P(_i32), _P(_i32),
+                                    _P(_i32)]),
     ("stencil_gs", _i32, [_P(Grid), _i32, _vp, _vp, _P(Weights), _i32, _dbl, _i32, _i32, _vp]),
+    ("stencil_sync", _i32, [_vp]),
+    ("stencil_gs_abort", _i32, [_i32]),
+    ("stencil_gs_spin_limit", _i32, [_i64]),
     ("stencil_rbgs", _i32, [_P(Grid), _i32, _vp, _vp, _vp, _P(Weights), _i32, _dbl, _i32, _i32, _vp]),
     ("stencil_residual", _i32, [_P(Grid), _vp, _vp, _vp, _P(_dbl), _vp]),
     ("stencil_refine_solve", _i32, [_P(Grid), _i32, _i32, _vp, _vp, _i32, _i32, _dbl, _i32,
@@ -186,6 +192,17 @@ def jacobi_plan(sweeps, t_fuse=0, fp32=False, rhs=False):
     return list(buf[:n.value]), bool(fc.value)
 
 
+def jacobi_tiles(shape, levels, fp32=False, rhs=False, halo=1):
+    """Tiling of one fused pass of `levels` levels over a padded grid of
+    `shape` (pz, py, px): (tile_w, tile_h, tiles, interior_tiles)."""
+    pz, py, px = shape
+    grid = Grid(px - 2 * halo, py - 2 * halo, pz - 2 * halo, halo)
+    out = [ctypes.c_int32(0) for _ in range(4)]
+    _check(lib().stencil_jacobi_tiles(ctypes.byref(grid), ST.FP32 if fp32 else ST.FP64,
+                                      int(bool(rhs)), int(levels), *[ctypes.byref(o) for o in out]))
+    return tuple(o.value for o in out)
+
+
 def red_black(u, scratch, sweeps, a=0.0, b=1.0 / 6.0, f=None, g=0.0, t_fuse=0, halo=1,
               bc=ST.BC_KEEP, bc_value=0.0, stream=None):
     """`sweeps` red-black Gauss-Seidel sweeps on u (result in u), t_fuse sweeps
@@ -213,11 +230,47 @@ def gauss_seidel(u, sweeps, a=0.0, b=1.0 / 6.0, f=None, g=0.0, t_fuse=0, halo=1,
     return u
 
 
-def residual(u, fp, r=None, halo=1, stream=None):
-    """r = f' - (6c - s) (FP64); returns the deterministic sum of r^2."""
+def _check_fp64_interior(u, t, name, halo):
+    """t must be None or an FP64 interior-only array matching the grid u."""
+    import torch
+    if t is None:
+        return
+    pz, py, px = u.shape
+    if t.dtype != torch.float64:
+        raise TypeError("%s must be float64" % name)
+    if tuple(t.shape) != (pz - 2 * halo, py - 2 * halo, px - 2 * halo):
+        raise ValueError("%s must be interior-only, shape (nz, ny, nx)" % name)
+
+
+def _check_fp64_grid(u):
     import torch
     if u.dtype != torch.float64:
-        raise TypeError("residual works on FP64 grids")
+        raise TypeError("u must be a float64 grid")
+    if u.dim() != 3:
+        raise ValueError("u must be a 3-D padded grid")
+
+
+def sync(stream=None):
+    """Wait for the stream; raises StencilError (EHIP) if a Gauss-Seidel
+    wavefront launch on this device gave up waiting since the last sync."""
+    _check(lib().stencil_sync(_stream(stream)))
+
+
+def gs_abort(device=0):
+    """Raise the device's wavefront abort word (cleared by sync())."""
+    _check(lib().stencil_gs_abort(int(device)))
+
+
+def gs_spin_limit(polls=0):
+    """Polls of one wavefront wait before it gives up (0 = default)."""
+    _check(lib().stencil_gs_spin_limit(int(polls)))
+
+
+def residual(u, fp, r=None, halo=1, stream=None):
+    """r = f' - (6c - s) (FP64); returns the deterministic sum of r^2."""
+    _check_fp64_grid(u)
+    _check_fp64_interior(u, fp, "fp", halo)
+    _check_fp64_interior(u, r, "r", halo)
     grid = _dims(u, halo)
     out = ctypes.c_double(0.0)
     _check(lib().stencil_residual(ctypes.byref(grid), _dev_ptr(u, "u"), _dev_ptr(fp, "fp"),
@@ -230,6 +283,10 @@ def refine_solve(u, fp, method=0, inner_fp32=True, inner_sweeps=16, t_fuse=0, re
     """Solve A u = f' by FP64 defect correction around an FP32 (or FP64) smoother.
 
     Returns (outer_rounds, relative_residual, status)."""
+    _check_fp64_grid(u)
+    if fp is None:
+        raise ValueError("fp is required")
+    _check_fp64_interior(u, fp, "fp", halo)
     grid = _dims(u, halo)
     od = ctypes.c_int32(0)
     rel = ctypes.c_double(0.0)

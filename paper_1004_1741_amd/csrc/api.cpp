@@ -150,17 +150,31 @@ int run_rbgs(const Geom &g, bool fp32, void *u, void *scratch, const void *f, do
     return ST_OK;
 }
 
+// Sweeps in flight per wavefront launch: t_fuse, or all (at most 4095).
 int run_gs(const Geom &g, bool fp32, void *u, const void *f, double a, double b, double gw,
            int sweeps, int t_fuse, hipStream_t s) {
     int per = t_fuse == 0 ? 4095 : t_fuse;
     if (per > 4095) per = 4095;
+    // one launch holds fewer than 2^31 (sweep, bundle) items
+    const int64_t bundles = (int64_t)((g.ny + 7) / 8) * ((g.nz + 7) / 8);
+    if ((int64_t)per * bundles >= ((int64_t)1 << 31)) per = (int)((((int64_t)1 << 31) - 1) / bundles);
     for (int done = 0; done < sweeps; done += per) {
         const int n = sweeps - done < per ? sweeps - done : per;
-        std::string err;
-        hipError_t e = launch_gs(fp32, g, u, f, a, b, gw, n, s, &err);
-        if (e != hipSuccess)
-            return err.empty() ? hip_fail(e, "gauss-seidel launch") : fail(ST_EINVAL, err);
+        HIP_TRY(launch_gs(fp32, g, u, f, a, b, gw, n, s), "gauss-seidel launch");
     }
+    return ST_OK;
+}
+
+// ST_EHIP (and clears the flag) if a wavefront launch on the current device
+// gave up waiting; synchronizes s.
+int check_gs_status(hipStream_t s) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "device");
+    uint32_t st = 0;
+    HIP_TRY(gs_status(dev, s, true, &st), "gauss-seidel status");
+    if (st & 1u)
+        return fail(ST_EHIP, "a Gauss-Seidel wavefront launch gave up waiting (spin limit "
+                             "reached or abort requested); its grid holds partial results");
     return ST_OK;
 }
 
@@ -213,6 +227,24 @@ int stencil_jacobi_plan(int32_t dtype, int32_t has_rhs, int32_t sweeps, int32_t 
     if (t_list)
         for (int i = 0; i < (int)p.size() && i < max_list; ++i) t_list[i] = p[i];
     if (final_copy) *final_copy = fc ? 1 : 0;
+    return ST_OK;
+}
+
+int stencil_jacobi_tiles(const st_grid *grid, int32_t dtype, int32_t has_rhs, int32_t levels,
+                         int32_t *tile_w, int32_t *tile_h, int32_t *tiles, int32_t *interior) {
+    Geom g;
+    int rc = check_grid(grid, &g);
+    if (rc) return rc;
+    if (dtype != ST_FP64 && dtype != ST_FP32) return fail(ST_EINVAL, "dtype must be FP64 or FP32");
+    if (levels < 1 || levels > 8) return fail(ST_EINVAL, "levels must be 1..8");
+    const bool fp32 = dtype == ST_FP32;
+    const JacTileCfg c = jacobi_tile_cfg(fp32, levels, has_rhs != 0);
+    int nt = 0, ni = 0;
+    jacobi_tile_count(fp32, levels, has_rhs != 0, g, &nt, &ni);
+    if (tile_w) *tile_w = c.ow();
+    if (tile_h) *tile_h = c.oh();
+    if (tiles) *tiles = nt;
+    if (interior) *interior = ni;
     return ST_OK;
 }
 
@@ -284,6 +316,22 @@ int stencil_gs(const st_grid *grid, int32_t dtype, void *u, const void *f, const
     return run_gs(g, fp32, u, f, w->center, w->neighbor, f ? w->rhs : 0.0, sweeps, t_fuse, s);
 }
 
+int stencil_sync(void *hip_stream) { return check_gs_status((hipStream_t)hip_stream); }
+
+int stencil_gs_abort(int32_t device) {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n)
+        return fail(ST_EINVAL, "no such HIP device");
+    HIP_TRY(gs_abort(device), "gauss-seidel abort");
+    return ST_OK;
+}
+
+int stencil_gs_spin_limit(int64_t polls) {
+    if (polls < 0 || polls > 0xffffffffll) return fail(ST_EINVAL, "polls must be 0..2^32-1");
+    gs_set_spin_limit((uint32_t)polls);
+    return ST_OK;
+}
+
 int stencil_residual(const st_grid *grid, const double *u, const double *fp, double *r_or_null,
                      double *norm2_out, void *hip_stream) {
     Geom g;
@@ -342,18 +390,13 @@ int stencil_refine_solve(const st_grid *grid, int32_t method, int32_t inner_dtyp
     } else if (method != 1) {
         HIP_TRY(sbuf.alloc((size_t)np * sizeof(double)), "refine workspace");
     }
-    // ||f'|| with the same deterministic reduction (residual of u = 0 is f')
-    {
-        DevBuf zero;
-        HIP_TRY(zero.alloc((size_t)np * sizeof(double)), "refine workspace");
-        HIP_TRY(hipMemsetAsync(zero.p, 0, (size_t)np * sizeof(double), s), "memset");
-        HIP_TRY(launch_residual_poisson(g, (const double *)zero.p, fp, nullptr, nullptr, partials,
-                                        nullptr, s), "norm f");
-        HIP_TRY(launch_sum_partials(partials, nb, dsum + 1, s), "norm f");
-        HIP_TRY(hipStreamSynchronize(s), "sync");
-    }
+    // ||f'|| with the same deterministic reduction (the residual of u = 0 is f')
+    HIP_TRY(launch_residual_poisson(g, nullptr, fp, nullptr, nullptr, partials, nullptr, s),
+            "norm f");
+    HIP_TRY(launch_sum_partials(partials, nb, dsum + 1, s), "norm f");
     double ff = 0.0;
-    HIP_TRY(hipMemcpy(&ff, dsum + 1, sizeof(double), hipMemcpyDeviceToHost), "copy");
+    HIP_TRY(hipMemcpyAsync(&ff, dsum + 1, sizeof(double), hipMemcpyDeviceToHost, s), "copy");
+    HIP_TRY(hipStreamSynchronize(s), "sync");
     const double nf = std::sqrt(ff);
     if (f32) {
         HIP_TRY(hipMemsetAsync(ebuf.p, 0, (size_t)np * sizeof(float), s), "memset");
@@ -404,6 +447,10 @@ int stencil_refine_solve(const st_grid *grid, int32_t method, int32_t inner_dtyp
             if (rc) return rc;
         }
         ++outer;
+        if (method == 1) {  // the round's wavefront launches must have completed normally
+            rc = check_gs_status(s);
+            if (rc) return rc;
+        }
     }
     HIP_TRY(hipStreamSynchronize(s), "sync");
     if (outer_done) *outer_done = outer;

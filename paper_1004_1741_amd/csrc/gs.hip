@@ -88,12 +88,25 @@ struct GsJob {
     uint32_t *progress;  // [sweep][bundle]: chunks stored so far
 };
 
+// Control block of one device.
+// abort: set by a wave that gave up waiting, or by the host
+// (stencil_gs_abort); every wait and every ticket fetch checks it, so all
+// waves then finish their items without waiting and exit.  status: bit 0 is
+// set by a wave that gave up; read and cleared by the host (stencil_sync).
+struct GsCtl {
+    uint32_t abort;
+    uint32_t status;
+    uint32_t pad_[62];
+};
+
 template <typename T>
 struct GsArgs {
     GsJob<T> job;
     uint32_t nitems;
     const uint32_t *items;   // (tau << 20) | (J << 10) | K, topologically ordered
     uint32_t *ticket;
+    GsCtl *ctl;
+    uint32_t spin_limit;     // polls of one wait before giving up
 };
 
 // Batched launch: items of several jobs merged in key order; each item is
@@ -104,6 +117,8 @@ struct GsBatchArgs {
     uint32_t nitems;
     const uint64_t *items;
     uint32_t *ticket;
+    GsCtl *ctl;
+    uint32_t spin_limit;
 };
 
 // Bundle data crosses workgroups that may sit on different XCDs, whose L2
@@ -129,9 +144,17 @@ __device__ __forceinline__ void wait_vm_done() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
 }
 
-__device__ __forceinline__ void wait_at_least(const uint32_t *p, uint32_t need) {
-    while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need)
-        __builtin_amdgcn_s_sleep(2);
+// A wave that gives up raises the device's abort word (seen by every other
+// wait within 64 polls) and records the failure for the host.
+__device__ __forceinline__ void give_up(GsCtl *ctl) {
+    if (threadIdx.x == 0) {
+        __hip_atomic_store(&ctl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_or(&ctl->status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+__device__ __forceinline__ bool aborted(const GsCtl *ctl) {
+    return __hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
 }
 
 // slot index (10x10 grid, jl fastest) of the li-th non-corner staged line
@@ -144,7 +167,7 @@ __device__ __forceinline__ int staged_slot(int li) {
 // One work item: sweep tau of bundle (J, K) of one grid, marched along x.
 template <typename T, bool HAS_A, bool HAS_F>
 __device__ __forceinline__ void gs_item(const GsJob<T> &A, int tau, int J, int K, T *ring,
-                                        T *fring) {
+                                        T *fring, GsCtl *ctl, uint32_t spin_limit) {
     const int lane = threadIdx.x;
     const int kk = lane & 7, jj = lane >> 3;  // kk fastest: conflict-free LDS
     const int d = jj + kk;                    // skew of this lane's line
@@ -220,8 +243,12 @@ __device__ __forceinline__ void gs_item(const GsJob<T> &A, int tau, int J, int K
                                   Pcur + me - A.nj};
         const bool has[5] = {tau > 0, tau > 0 && J + 1 < A.nj, tau > 0 && K + 1 < A.nk, J > 0,
                              K > 0};
+        // Every wait is bounded: after spin_limit polls, or once the abort word
+        // is raised, the wave gives up and runs the rest of the item without
+        // waiting (its results are then invalid and the launch reports it).
+        bool dead = false;
         auto wait_chunk = [&](int c) {
-            if (c >= A.ncs) return;  // only positions >= nx: never written
+            if (c >= A.ncs || dead) return;  // c >= ncs: only positions >= nx, never written
             const uint32_t need = (uint32_t)c + 1u;
             uint32_t v[5];
 #pragma unroll
@@ -229,9 +256,16 @@ __device__ __forceinline__ void gs_item(const GsJob<T> &A, int tau, int J, int K
                 v[q] = has[q] ? __hip_atomic_load(dep[q], __ATOMIC_RELAXED,
                                                   __HIP_MEMORY_SCOPE_AGENT)
                               : need;
+            uint32_t polls = 0;
 #pragma unroll
             for (int q = 0; q < 5; ++q)
                 while (v[q] < need) {
+                    ++polls;
+                    if (polls >= spin_limit || ((polls & 63u) == 0u && aborted(ctl))) {
+                        give_up(ctl);
+                        dead = true;
+                        return;
+                    }
                     __builtin_amdgcn_s_sleep(2);
                     v[q] = __hip_atomic_load(dep[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
@@ -363,19 +397,31 @@ __device__ __forceinline__ void gs_item(const GsJob<T> &A, int tau, int J, int K
         }
 }
 
+// Next ticket for this wave, or nitems (stop) once the abort word is raised;
+// a launch stopped that way reports it like a wait that gave up.
+__device__ __forceinline__ uint32_t next_ticket(uint32_t *ticket, uint32_t nitems, GsCtl *ctl) {
+    uint32_t t = 0;
+    if (threadIdx.x == 0) {
+        if (aborted(ctl)) {
+            __hip_atomic_fetch_or(&ctl->status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            t = nitems;
+        } else {
+            t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    return __shfl(t, 0, 64);
+}
+
 template <typename T, bool HAS_A, bool HAS_F>
 __global__ void __launch_bounds__(64) gs_wavefront_kernel(GsArgs<T> G) {
     __shared__ T ring[GsLds<T>::RING_LEN];
     __shared__ T fring[HAS_F ? GsLds<T>::FRING_LEN : 1];
     for (;;) {
-        uint32_t t = 0;
-        if (threadIdx.x == 0)
-            t = __hip_atomic_fetch_add(G.ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        t = __shfl(t, 0, 64);
+        const uint32_t t = next_ticket(G.ticket, G.nitems, G.ctl);
         if (t >= G.nitems) break;
         const uint32_t it = G.items[t];
         gs_item<T, HAS_A, HAS_F>(G.job, (int)(it >> 20), (int)((it >> 10) & 1023u),
-                                 (int)(it & 1023u), ring, fring);
+                                 (int)(it & 1023u), ring, fring, G.ctl, G.spin_limit);
     }
 }
 
@@ -384,90 +430,153 @@ __global__ void __launch_bounds__(64) gs_batch_kernel(GsBatchArgs<T> G) {
     __shared__ T ring[GsLds<T>::RING_LEN];
     __shared__ T fring[HAS_F ? GsLds<T>::FRING_LEN : 1];
     for (;;) {
-        uint32_t t = 0;
-        if (threadIdx.x == 0)
-            t = __hip_atomic_fetch_add(G.ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        t = __shfl(t, 0, 64);
+        const uint32_t t = next_ticket(G.ticket, G.nitems, G.ctl);
         if (t >= G.nitems) break;
         const uint64_t it = G.items[t];
         const GsJob<T> job = G.jobs[(int)(it >> 48)];
         gs_item<T, HAS_A, HAS_F>(job, (int)((it >> 32) & 0xffffu), (int)((it >> 16) & 0xffffu),
-                                 (int)(it & 0xffffu), ring, fring);
+                                 (int)(it & 0xffffu), ring, fring, G.ctl, G.spin_limit);
     }
 }
 
-__global__ void gs_reset_kernel(uint32_t *progress, int n, uint32_t *ticket) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+__global__ void gs_reset_kernel(uint32_t *progress, int64_t n, uint32_t *ticket) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
         progress[i] = 0u;
     if (blockIdx.x == 0 && threadIdx.x == 0) *ticket = 0u;
 }
 
-// ---- host side: item tables and flag buffers (library-owned) ----
+// ---- item table, built on the device for every launch ----
+// Items (tau, J, K) are ordered by key = 2*tau + J + K, then tau, then J.
+// Bundles J of a "rest" r = key - 2*tau run over [max(0, r - nk + 1),
+// min(nj - 1, r)].
+__device__ __forceinline__ int rest_lo(int r, int nk) { return r - (nk - 1) > 0 ? r - (nk - 1) : 0; }
+__device__ __forceinline__ int rest_count(int r, int nj, int nk) {
+    if (r < 0) return 0;
+    const int hi = r < nj - 1 ? r : nj - 1;
+    const int lo = rest_lo(r, nk);
+    return hi >= lo ? hi - lo + 1 : 0;
+}
+// first tau whose rest r = key - 2 tau can be a valid J + K (r <= nj + nk - 2)
+__device__ __forceinline__ int tau_first(int key, int nj, int nk) {
+    const int d = key - (nj + nk - 2);
+    return d > 0 ? (d + 1) / 2 : 0;
+}
 
-struct GsBuffers {
-    uint32_t *progress = nullptr;
-    uint32_t *ticket = nullptr;
-    int cap = 0;
-};
-
-std::mutex g_gs_mu;
-// Progress counters and the ticket are reset at the start of every launch, so
-// launches that may run concurrently (different streams) get separate ones;
-// launches on one stream are ordered and can share them.
-std::map<std::pair<int, hipStream_t>, GsBuffers> g_gs_bufs;
-std::map<std::tuple<int, int, int, int>, uint32_t *> g_gs_items;  // (dev, nj, nk, S)
-
-hipError_t get_items(int dev, int nj, int nk, int S, uint32_t **out, uint32_t *count) {
-    auto key = std::make_tuple(dev, nj, nk, S);
-    *count = (uint32_t)S * nj * nk;
-    auto itx = g_gs_items.find(key);
-    if (itx != g_gs_items.end()) {
-        *out = itx->second;
-        return hipSuccess;
+// One block: prefix[key] = number of items with a smaller key; clears the
+// ticket.  nkeys = 2 (S - 1) + nj + nk - 1.
+__global__ void __launch_bounds__(1024) gs_prefix_kernel(int S, int nj, int nk,
+                                                         uint32_t *__restrict__ prefix,
+                                                         uint32_t *__restrict__ ticket) {
+    __shared__ uint32_t part[1024];
+    const int nkeys = 2 * (S - 1) + nj + nk - 1;
+    const int per = (nkeys + 1023) / 1024;
+    const int k0 = threadIdx.x * per;
+    uint32_t local = 0;
+    for (int k = k0; k < k0 + per && k < nkeys; ++k) {
+        const int t1 = min(S - 1, k / 2);
+        for (int tau = tau_first(k, nj, nk); tau <= t1; ++tau)
+            local += (uint32_t)rest_count(k - 2 * tau, nj, nk);
     }
-    std::vector<uint32_t> items;
-    items.reserve(*count);
-    const int kmax = 2 * (S - 1) + (nj - 1) + (nk - 1);
-    for (int key2 = 0; key2 <= kmax; ++key2)
-        for (int tau = 0; tau < S; ++tau) {
-            const int rest = key2 - 2 * tau;
-            if (rest < 0) break;
-            for (int J = 0; J < nj; ++J) {
-                const int K = rest - J;
-                if (K < 0) break;
-                if (K >= nk) continue;
-                items.push_back(((uint32_t)tau << 20) | ((uint32_t)J << 10) | (uint32_t)K);
-            }
-        }
-    uint32_t *d = nullptr;
-    hipError_t e = hipMalloc(&d, items.size() * sizeof(uint32_t));
-    if (e != hipSuccess) return e;
-    e = hipMemcpy(d, items.data(), items.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-        (void)hipFree(d);
-        return e;
+    part[threadIdx.x] = local;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {  // inclusive scan of the chunk sums
+        const uint32_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
     }
-    g_gs_items[key] = d;
-    *out = d;
+    uint32_t run = threadIdx.x > 0 ? part[threadIdx.x - 1] : 0u;
+    for (int k = k0; k < k0 + per && k < nkeys; ++k) {
+        prefix[k] = run;
+        const int t1 = min(S - 1, k / 2);
+        for (int tau = tau_first(k, nj, nk); tau <= t1; ++tau)
+            run += (uint32_t)rest_count(k - 2 * tau, nj, nk);
+    }
+    if (threadIdx.x == 0) {
+        prefix[nkeys] = part[1023];
+        *ticket = 0u;
+    }
+}
+
+// One thread per item: writes it at its position in key order and clears its
+// progress counter.
+__global__ void __launch_bounds__(256) gs_items_kernel(int S, int nj, int nk,
+                                                       const uint32_t *__restrict__ prefix,
+                                                       uint32_t *__restrict__ items,
+                                                       uint32_t *__restrict__ progress) {
+    const int64_t n = (int64_t)S * nj * nk;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int nb = nj * nk;
+    const int tau = (int)(i / nb);
+    const int rem = (int)(i - (int64_t)tau * nb);
+    const int K = rem / nj, J = rem - K * nj;
+    const int key = 2 * tau + J + K;
+    uint32_t pos = prefix[key];
+    for (int t = tau_first(key, nj, nk); t < tau; ++t) pos += (uint32_t)rest_count(key - 2 * t, nj, nk);
+    pos += (uint32_t)(J - rest_lo(key - 2 * tau, nk));
+    items[pos] = ((uint32_t)tau << 20) | ((uint32_t)J << 10) | (uint32_t)K;
+    progress[i] = 0u;
+}
+
+// ---- per-device control block ----
+// One GsCtl per device, a static device variable.  Host code never uses the
+// variable's name as an address: the device address comes from
+// hipGetSymbolAddress, looked up once per device with that device current.
+__device__ GsCtl gs_ctl;
+
+__global__ void gs_ctl_clear_kernel(GsCtl *ctl) {
+    if (threadIdx.x == 0) {
+        ctl->abort = 0u;
+        ctl->status = 0u;
+    }
+}
+
+std::mutex g_ctl_mu;
+GsCtl *g_ctl_ptr[64];                       // device address of gs_ctl, per device
+hipStream_t g_ctl_stream[64];               // for host writes while kernels run
+std::atomic<uint32_t> g_spin_limit{1u << 24};
+
+// Device address of this device's control block (looked up and cleared on
+// first use; the clear is a kernel on stream s, ordered before the caller's
+// work).
+hipError_t device_ctl(int dev, hipStream_t s, GsCtl **out) {
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_ctl_mu);
+    if (!g_ctl_ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(gs_ctl));
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(gs_ctl_clear_kernel, dim3(1), dim3(64), 0, s, static_cast<GsCtl *>(p));
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        g_ctl_ptr[dev] = static_cast<GsCtl *>(p);
+    }
+    *out = g_ctl_ptr[dev];
     return hipSuccess;
 }
 
-hipError_t get_bufs(int dev, hipStream_t s, int ncounters, GsBuffers **out) {
-    GsBuffers &B = g_gs_bufs[std::make_pair(dev, s)];
-    if (B.cap < ncounters) {
-        if (B.progress) (void)hipFree(B.progress);
-        if (B.ticket) (void)hipFree(B.ticket);
-        B.progress = nullptr;
-        B.ticket = nullptr;
-        B.cap = 0;
-        hipError_t e = hipMalloc(&B.progress, (size_t)ncounters * sizeof(uint32_t));
-        if (e != hipSuccess) return e;
-        e = hipMalloc(&B.ticket, 256);
-        if (e != hipSuccess) return e;
-        B.cap = ncounters;
-    }
-    *out = &B;
-    return hipSuccess;
+// Workspace of one launch of S sweeps over nj x nk bundles, laid out from
+// `base` (may be nullptr to only compute the size).
+struct GsWork {
+    uint32_t *progress, *ticket, *prefix, *items;
+    size_t bytes;
+};
+GsWork gs_work_layout(int S, int nj, int nk, unsigned char *base) {
+    auto up = [](size_t n) { return (n + 255) / 256 * 256; };
+    const size_t nitems = (size_t)S * nj * nk;
+    const size_t nkeys = (size_t)2 * (S - 1) + nj + nk - 1;
+    const size_t o_ticket = up(nitems * 4);
+    const size_t o_prefix = o_ticket + 256;
+    const size_t o_items = o_prefix + up((nkeys + 1) * 4);
+    GsWork w;
+    w.bytes = o_items + up(nitems * 4);
+    w.progress = reinterpret_cast<uint32_t *>(base);
+    w.ticket = reinterpret_cast<uint32_t *>(base + o_ticket);
+    w.prefix = reinterpret_cast<uint32_t *>(base + o_prefix);
+    w.items = reinterpret_cast<uint32_t *>(base + o_items);
+    return w;
 }
 
 template <typename T>
@@ -513,53 +622,49 @@ int per_cu_occupancy(K kfn) {
     return per_cu;
 }
 
+// One launch of S sweeps.  ws: workspace of gs_work_layout(S, nj, nk) bytes
+// on the device; the item table is built there by two small kernels.
 template <typename T, bool HAS_A, bool HAS_F>
 hipError_t launch_gs_t(const Geom &g, void *u, const void *f, double a, double b, double gw,
-                       int S, hipStream_t s, std::string *err) {
+                       int S, GsCtl *ctl, unsigned char *ws, hipStream_t s) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     GsArgs<T> G;
     G.job = make_job<T>(g, u, f, a, b, gw, nullptr);
     const int nj = G.job.nj, nk = G.job.nk;
-    if (nj > 1024 || nk > 1024 || S > 4095) {
-        if (err) *err = "Gauss-Seidel grid too large for one launch (ny, nz <= 8192)";
-        return hipErrorInvalidValue;
-    }
-    {
-        std::lock_guard<std::mutex> lk(g_gs_mu);
-        GsBuffers *B = nullptr;
-        e = get_bufs(dev, s, S * nj * nk, &B);
-        if (e != hipSuccess) return e;
-        uint32_t *items = nullptr;
-        e = get_items(dev, nj, nk, S, &items, &G.nitems);
-        if (e != hipSuccess) return e;
-        G.items = items;
-        G.job.progress = B->progress;
-        G.ticket = B->ticket;
-    }
-    hipLaunchKernelGGL(gs_reset_kernel, dim3(256), dim3(256), 0, s, G.job.progress, S * nj * nk,
-                       G.ticket);
+    const GsWork w = gs_work_layout(S, nj, nk, ws);
+    const int64_t nitems = (int64_t)S * nj * nk;
+    hipLaunchKernelGGL(gs_prefix_kernel, dim3(1), dim3(1024), 0, s, S, nj, nk, w.prefix, w.ticket);
+    hipLaunchKernelGGL(gs_items_kernel, dim3((unsigned)((nitems + 255) / 256)), dim3(256), 0, s, S,
+                       nj, nk, (const uint32_t *)w.prefix, w.items, w.progress);
+    G.nitems = (uint32_t)nitems;
+    G.items = w.items;
+    G.ticket = w.ticket;
+    G.job.progress = w.progress;
+    G.ctl = ctl;
+    G.spin_limit = g_spin_limit.load(std::memory_order_relaxed);
     static std::atomic<int> per_cu_cached{0};
     int per_cu = per_cu_cached.load(std::memory_order_relaxed);
     if (per_cu == 0) {
         per_cu = per_cu_occupancy(gs_wavefront_kernel<T, HAS_A, HAS_F>);
         per_cu_cached.store(per_cu, std::memory_order_relaxed);
     }
-    int grid = per_cu * device_cus(dev);
-    if ((uint32_t)grid > G.nitems) grid = (int)G.nitems;
-    hipLaunchKernelGGL((gs_wavefront_kernel<T, HAS_A, HAS_F>), dim3(grid), dim3(64), 0, s, G);
+    int64_t grid = (int64_t)per_cu * device_cus(dev);
+    if (grid > nitems) grid = nitems;
+    hipLaunchKernelGGL((gs_wavefront_kernel<T, HAS_A, HAS_F>), dim3((unsigned)grid), dim3(64), 0,
+                       s, G);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_gs_any(const Geom &g, void *u, const void *f, double a, double b, double gw,
-                         int S, hipStream_t s, std::string *err) {
+                         int S, GsCtl *ctl, unsigned char *ws, hipStream_t s) {
     const bool ha = a != 0.0, hf = f != nullptr;
-    if (ha && hf) return launch_gs_t<T, true, true>(g, u, f, a, b, gw, S, s, err);
-    if (ha) return launch_gs_t<T, true, false>(g, u, f, a, b, gw, S, s, err);
-    if (hf) return launch_gs_t<T, false, true>(g, u, f, a, b, gw, S, s, err);
-    return launch_gs_t<T, false, false>(g, u, f, a, b, gw, S, s, err);
+    if (ha && hf) return launch_gs_t<T, true, true>(g, u, f, a, b, gw, S, ctl, ws, s);
+    if (ha) return launch_gs_t<T, true, false>(g, u, f, a, b, gw, S, ctl, ws, s);
+    if (hf) return launch_gs_t<T, false, true>(g, u, f, a, b, gw, S, ctl, ws, s);
+    return launch_gs_t<T, false, false>(g, u, f, a, b, gw, S, ctl, ws, s);
 }
 
 // ---- batched launch (job service) ----
@@ -610,6 +715,7 @@ hipError_t launch_gs_batch_t(const std::vector<GsBatchItem> &items, GsBatchWork 
     const size_t off_prog = off_items + up256(items_bytes);
     const size_t off_ticket = off_prog + up256(ncount * sizeof(uint32_t));
     const size_t need = off_ticket + 256;
+    if (ncount > 0xffffffffull || w.items.size() > 0xffffffffull) return hipErrorInvalidValue;
     if (w.dev_bytes < need) {
         if (w.dev) (void)hipFree(w.dev);
         w.dev = nullptr;
@@ -632,12 +738,16 @@ hipError_t launch_gs_batch_t(const std::vector<GsBatchItem> &items, GsBatchWork 
     if (e != hipSuccess) return e;
     e = hipMemcpyAsync(ditems, w.items.data(), items_bytes, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(gs_reset_kernel, dim3(256), dim3(256), 0, s, dprog, (int)ncount, dticket);
+    hipLaunchKernelGGL(gs_reset_kernel, dim3(256), dim3(256), 0, s, dprog, (int64_t)ncount,
+                       dticket);
     GsBatchArgs<T> G;
     G.jobs = djobs;
     G.nitems = (uint32_t)w.items.size();
     G.items = ditems;
     G.ticket = dticket;
+    e = device_ctl(dev, s, &G.ctl);
+    if (e != hipSuccess) return e;
+    G.spin_limit = g_spin_limit.load(std::memory_order_relaxed);
     static std::atomic<int> per_cu_cached{0};
     int per_cu = per_cu_cached.load(std::memory_order_relaxed);
     if (per_cu == 0) {
@@ -662,9 +772,77 @@ hipError_t launch_gs_batch_any(bool ha, bool hf, const std::vector<GsBatchItem> 
 }  // namespace
 
 hipError_t launch_gs(bool fp32, const Geom &g, void *u, const void *f, double a, double b,
-                     double gw, int sweeps, hipStream_t s, std::string *err) {
-    return fp32 ? launch_gs_any<float>(g, u, f, a, b, gw, sweeps, s, err)
-                : launch_gs_any<double>(g, u, f, a, b, gw, sweeps, s, err);
+                     double gw, int sweeps, hipStream_t s) {
+    if (sweeps < 1 || sweeps > 4095) return hipErrorInvalidValue;
+    if ((int64_t)sweeps * ((g.ny + 7) / 8) * ((g.nz + 7) / 8) >= ((int64_t)1 << 31))
+        return hipErrorInvalidValue;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    GsCtl *ctl = nullptr;
+    e = device_ctl(dev, s, &ctl);
+    if (e != hipSuccess) return e;
+    const int nj = (g.ny + 7) / 8, nk = (g.nz + 7) / 8;
+    // stream-ordered workspace, returned to the stream's pool after the launch
+    const size_t bytes = gs_work_layout(sweeps, nj, nk, nullptr).bytes;
+    void *ws = nullptr;
+    e = hipMallocAsync(&ws, bytes, s);
+    if (e != hipSuccess) return e;
+    e = fp32 ? launch_gs_any<float>(g, u, f, a, b, gw, sweeps, ctl,
+                                    static_cast<unsigned char *>(ws), s)
+             : launch_gs_any<double>(g, u, f, a, b, gw, sweeps, ctl,
+                                     static_cast<unsigned char *>(ws), s);
+    const hipError_t ef = hipFreeAsync(ws, s);
+    return e != hipSuccess ? e : ef;
+}
+
+hipError_t gs_status(int dev, hipStream_t s, bool clear, uint32_t *status) {
+    GsCtl *ctl = nullptr;
+    hipError_t e = device_ctl(dev, s, &ctl);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    uint32_t st = 0;
+    e = hipMemcpyAsync(&st, &ctl->status, sizeof(st), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    if (clear) {
+        hipLaunchKernelGGL(gs_ctl_clear_kernel, dim3(1), dim3(64), 0, s, ctl);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return e;
+    }
+    *status = st;
+    return hipSuccess;
+}
+
+hipError_t gs_abort(int dev) {
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (dev != cur) {
+        e = hipSetDevice(dev);
+        if (e != hipSuccess) return e;
+    }
+    hipStream_t st = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_ctl_mu);
+        if (!g_ctl_stream[dev]) e = hipStreamCreateWithFlags(&g_ctl_stream[dev], hipStreamNonBlocking);
+        st = g_ctl_stream[dev];
+    }
+    GsCtl *ctl = nullptr;
+    if (e == hipSuccess) e = device_ctl(dev, st, &ctl);
+    // written on a stream of its own so that it lands while wavefront
+    // launches on other streams are running
+    static const uint32_t one = 1u;
+    if (e == hipSuccess) e = hipMemcpyAsync(&ctl->abort, &one, sizeof(one), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (dev != cur) (void)hipSetDevice(cur);
+    return e;
+}
+
+void gs_set_spin_limit(uint32_t polls) {
+    g_spin_limit.store(polls ? polls : (1u << 24), std::memory_order_relaxed);
 }
 
 hipError_t launch_gs_batch(bool fp32, bool has_a, bool has_f,

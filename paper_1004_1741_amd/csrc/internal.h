@@ -31,7 +31,9 @@ struct JacTileCfg {
     int oh() const { return ty() - 2 * tb; }             // output tile height
 };
 
-JacTileCfg jacobi_tile_cfg(bool fp32, int tb);
+JacTileCfg jacobi_tile_cfg(bool fp32, int tb, bool has_f);
+// x-y tiles of one fused pass over g, and how many take the unmasked path.
+void jacobi_tile_count(bool fp32, int tb, bool has_f, const Geom &g, int *tiles, int *interior);
 
 // One fused Jacobi pass: dst <- TB sweeps of src (interior only).
 // zc = output planes per z-chunk (0 = planner choice).
@@ -65,7 +67,8 @@ hipError_t launch_rbgs_pass(bool fp32, int sweeps, const Geom &g, const void *sr
 // own translation unit, the functions above dispatch on tb.
 template <int TB>
 struct JacobiLevels {
-    static JacTileCfg cfg(bool fp32);
+    static JacTileCfg cfg(bool fp32, bool has_f);
+    static void tiles(bool fp32, bool has_f, const Geom &g, int *tiles, int *interior);
     static hipError_t pass(bool fp32, const Geom &g, const void *src, void *dst, const void *f,
                            double a, double b, double gw, int zc, hipStream_t s);
     // red-black Gauss-Seidel: TB/2 sweeps in one pass (TB even)
@@ -98,9 +101,19 @@ int residual_partial_count(const Geom &g);
 // u(interior) += (double)e(interior); e padded float or double grid of same geometry.
 hipError_t launch_correct(const Geom &g, double *u, const void *e, bool e_fp32, hipStream_t s);
 
-// Gauss-Seidel wavefront (all sweeps of one launch).
+// Gauss-Seidel wavefront: one launch with all `sweeps` (1..4095) in flight.
+// Its workspace (progress counters, ticket, item table) is taken with
+// hipMallocAsync on s and released with hipFreeAsync after the launch.
 hipError_t launch_gs(bool fp32, const Geom &g, void *u, const void *f, double a, double b,
-                     double gw, int sweeps, hipStream_t s, std::string *err);
+                     double gw, int sweeps, hipStream_t s);
+// Synchronizes s, then reads (and optionally clears, with the abort word)
+// the device's wavefront status: bit 0 = a launch gave up waiting.
+hipError_t gs_status(int dev, hipStream_t s, bool clear, uint32_t *status);
+// Raises the device's abort word (running and later wavefront launches give
+// up at their next wait) until gs_status clears it.
+hipError_t gs_abort(int dev);
+// Polls of one wavefront wait before it gives up (0 = the default, 2^24).
+void gs_set_spin_limit(uint32_t polls);
 
 // Batched wavefront (job service): `sweeps` sweeps of every item's grid in
 // one launch; items of all grids share one ticket counter in key order.

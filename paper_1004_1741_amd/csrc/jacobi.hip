@@ -14,16 +14,29 @@ extern template struct JacobiLevels<6>;
 extern template struct JacobiLevels<7>;
 extern template struct JacobiLevels<8>;
 
-JacTileCfg jacobi_tile_cfg(bool fp32, int tb) {
+JacTileCfg jacobi_tile_cfg(bool fp32, int tb, bool has_f) {
     switch (tb) {
-        case 1: return JacobiLevels<1>::cfg(fp32);
-        case 2: return JacobiLevels<2>::cfg(fp32);
-        case 3: return JacobiLevels<3>::cfg(fp32);
-        case 4: return JacobiLevels<4>::cfg(fp32);
-        case 5: return JacobiLevels<5>::cfg(fp32);
-        case 6: return JacobiLevels<6>::cfg(fp32);
-        case 7: return JacobiLevels<7>::cfg(fp32);
-        default: return JacobiLevels<8>::cfg(fp32);
+        case 1: return JacobiLevels<1>::cfg(fp32, has_f);
+        case 2: return JacobiLevels<2>::cfg(fp32, has_f);
+        case 3: return JacobiLevels<3>::cfg(fp32, has_f);
+        case 4: return JacobiLevels<4>::cfg(fp32, has_f);
+        case 5: return JacobiLevels<5>::cfg(fp32, has_f);
+        case 6: return JacobiLevels<6>::cfg(fp32, has_f);
+        case 7: return JacobiLevels<7>::cfg(fp32, has_f);
+        default: return JacobiLevels<8>::cfg(fp32, has_f);
+    }
+}
+
+void jacobi_tile_count(bool fp32, int tb, bool has_f, const Geom &g, int *tiles, int *interior) {
+    switch (tb) {
+        case 1: return JacobiLevels<1>::tiles(fp32, has_f, g, tiles, interior);
+        case 2: return JacobiLevels<2>::tiles(fp32, has_f, g, tiles, interior);
+        case 3: return JacobiLevels<3>::tiles(fp32, has_f, g, tiles, interior);
+        case 4: return JacobiLevels<4>::tiles(fp32, has_f, g, tiles, interior);
+        case 5: return JacobiLevels<5>::tiles(fp32, has_f, g, tiles, interior);
+        case 6: return JacobiLevels<6>::tiles(fp32, has_f, g, tiles, interior);
+        case 7: return JacobiLevels<7>::tiles(fp32, has_f, g, tiles, interior);
+        default: return JacobiLevels<8>::tiles(fp32, has_f, g, tiles, interior);
     }
 }
 

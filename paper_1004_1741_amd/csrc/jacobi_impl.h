@@ -453,6 +453,18 @@ __device__ __forceinline__ void jacobi_tile(const JacArgs<T> &A, int tx, int ty,
     if (s <= s_end) step(s, P0, P1, F0, F1, Part{});
 }
 
+// A tile takes the unmasked path when its whole loaded footprint (the stored
+// tile plus TB sites on every side, x start aligned to the vector width) lies
+// inside the interior.  Shared by the kernels and the host-side tile count.
+template <int TB, int VX, int RY, int NW>
+__host__ __device__ __forceinline__ bool tile_interior(int h, int nx, int ny, int ow, int oh,
+                                                       int tx, int ty) {
+    int xs = h + tx * ow - TB;
+    xs -= ((xs % VX) + VX) % VX;
+    const int ys = h + ty * oh - TB;
+    return xs >= h && xs + 64 * VX <= h + nx && ys >= h && ys + NW * RY <= h + ny;
+}
+
 template <typename T, int TB, int VX, int RY, int NW, bool HAS_A, bool HAS_F, bool RB = false>
 __global__ void __launch_bounds__(NW * 64) jacobi_pass_kernel(JacArgs<T> A) {
     __shared__ T xch[2][TB][NW][2][64 * VX];
@@ -471,14 +483,7 @@ __global__ void __launch_bounds__(NW * 64) jacobi_pass_kernel(JacArgs<T> A) {
     const int ty = rem / A.tiles_x;
     const int tx = rem - ty * A.tiles_x;
 
-    // interior tile: the whole loaded footprint lies inside the interior
-    const int ox0 = A.h + tx * A.ow;
-    int xs = ox0 - TB;
-    xs -= ((xs % VX) + VX) % VX;
-    const int ys = A.h + ty * A.oh - TB;
-    const bool interior = xs >= A.h && xs + 64 * VX <= A.h + A.nx && ys >= A.h &&
-                          ys + NW * RY <= A.h + A.ny;
-    if (interior)
+    if (tile_interior<TB, VX, RY, NW>(A.h, A.nx, A.ny, A.ow, A.oh, tx, ty))
         jacobi_tile<T, TB, VX, RY, NW, HAS_A, HAS_F, false, RB>(A, tx, ty, cz, xch, fring);
     else
         jacobi_tile<T, TB, VX, RY, NW, HAS_A, HAS_F, true, RB>(A, tx, ty, cz, xch, fring);
@@ -518,13 +523,7 @@ __global__ void __launch_bounds__(NW * 64)
     const int rem = li - cz * tpc;
     const int ty = rem / A.tiles_x;
     const int tx = rem - ty * A.tiles_x;
-    const int ox0 = A.h + tx * A.ow;
-    int xs = ox0 - TB;
-    xs -= ((xs % VX) + VX) % VX;
-    const int ys = A.h + ty * A.oh - TB;
-    const bool interior = xs >= A.h && xs + 64 * VX <= A.h + A.nx && ys >= A.h &&
-                          ys + NW * RY <= A.h + A.ny;
-    if (interior)
+    if (tile_interior<TB, VX, RY, NW>(A.h, A.nx, A.ny, A.ow, A.oh, tx, ty))
         jacobi_tile<T, TB, VX, RY, NW, HAS_A, HAS_F, false>(A, tx, ty, cz, xch, fring);
     else
         jacobi_tile<T, TB, VX, RY, NW, HAS_A, HAS_F, true>(A, tx, ty, cz, xch, fring);
@@ -714,8 +713,33 @@ hipError_t launch_tb(const Geom &g, const void *src, void *dst, const void *f, d
 }  // namespace
 
 template <int TB>
-JacTileCfg JacobiLevels<TB>::cfg(bool fp32) {
+JacTileCfg JacobiLevels<TB>::cfg(bool fp32, bool has_f) {
+    if (has_f) return fp32 ? cfg_of<float, TB, true>() : cfg_of<double, TB, true>();
     return fp32 ? cfg_of<float, TB>() : cfg_of<double, TB>();
+}
+
+template <typename T, int TB, bool HAS_F>
+void count_tiles(const Geom &g, int *tiles, int *interior) {
+    using C = Cfg<T, TB, HAS_F>;
+    const JacTileCfg c = cfg_of<T, TB, HAS_F>();
+    const int ow = c.ow(), oh = c.oh();
+    const int tx = (g.nx + ow - 1) / ow, ty = (g.ny + oh - 1) / oh;
+    int in = 0;
+    for (int y = 0; y < ty; ++y)
+        for (int x = 0; x < tx; ++x)
+            in += tile_interior<TB, C::VX, C::RY, C::NW>(g.h, g.nx, g.ny, ow, oh, x, y) ? 1 : 0;
+    *tiles = tx * ty;
+    *interior = in;
+}
+
+template <int TB>
+void JacobiLevels<TB>::tiles(bool fp32, bool has_f, const Geom &g, int *tiles, int *interior) {
+    if (fp32)
+        has_f ? count_tiles<float, TB, true>(g, tiles, interior)
+              : count_tiles<float, TB, false>(g, tiles, interior);
+    else
+        has_f ? count_tiles<double, TB, true>(g, tiles, interior)
+              : count_tiles<double, TB, false>(g, tiles, interior);
 }
 
 template <int TB>

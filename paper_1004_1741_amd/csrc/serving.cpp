@@ -137,17 +137,21 @@ void finish(smooth_ctx *c, Job *j, int32_t state) {
 }
 
 // Admission (mu held): FIFO, but a job that does not fit lets later ones
-// pass at most 8 times; after that admission waits for it.
+// pass at most 8 times (counted when a later job is actually admitted ahead
+// of it); after that admission waits for it.
 void admit(smooth_ctx *c) {
+    std::vector<Job *> skipped;  // jobs ahead of the current one that did not fit
     for (auto it = c->pending.begin(); it != c->pending.end();) {
         if ((int)c->resident.size() >= c->cfg.max_inflight) break;
         Job *j = *it;
         uint64_t off = 0;
         if (!c->alloc.alloc(j->bytes, &off)) {
-            if (++j->bypassed > 8) break;
+            if (j->bypassed >= 8) break;
+            skipped.push_back(j);
             ++it;
             continue;
         }
+        for (Job *sk : skipped) ++sk->bypassed;
         j->off = off;
         j->allocated = true;
         char *base = static_cast<char *>(c->pool) + off;
@@ -239,14 +243,15 @@ struct GsGroup {
 // One iteration over the jobs in `act` (scheduler thread, mu not held).
 // Returns the jobs whose computation was completed in this iteration.
 hipError_t run_iteration(smooth_ctx *c, const std::vector<Job *> &act, int64_t batch,
-                         std::vector<Job *> *completed, std::vector<Job *> *failed) {
+                         std::vector<Job *> *completed, std::vector<Job *> *failed,
+                         std::vector<Job *> *gs_ran) {
     hipStream_t s = c->s_comp;
     std::map<int, JacGroup> jg;
     std::map<int, GsGroup> gg;
-    hipError_t e = hipSuccess;
     for (Job *j : act) {
         const double a = j->spec.weights.center, b = j->spec.weights.neighbor;
         const bool ha = a != 0.0;
+        hipError_t e = hipSuccess;  // this job's set-up only
         if (j->ph == PH_READY) {
             j->st.t_start_ns = now_ns();
             j->st.batch_id = (int32_t)batch;
@@ -314,6 +319,7 @@ hipError_t run_iteration(smooth_ctx *c, const std::vector<Job *> &act, int64_t b
     // batched launches
     for (auto &kv : jg) {
         JacGroup &G = kv.second;
+        hipError_t e = hipSuccess;
         auto &tab = c->jac_tables[kv.first];
         const size_t need = jacobi_batch_table_bytes((int)G.items.size());
         if (tab.second < need) {
@@ -327,7 +333,6 @@ hipError_t run_iteration(smooth_ctx *c, const std::vector<Job *> &act, int64_t b
             e = launch_jacobi_batch(G.fp32, G.tb, G.ha, G.hf, G.items, tab.first, G.staging, s);
         if (e != hipSuccess) {
             for (Job *j : G.jobs) failed->push_back(j);
-            e = hipSuccess;
             continue;
         }
         for (Job *j : G.jobs) {
@@ -339,14 +344,14 @@ hipError_t run_iteration(smooth_ctx *c, const std::vector<Job *> &act, int64_t b
         GsGroup &G = kv.second;
         auto &w = c->gs_works[kv.first];
         if (!w) w.reset(new GsBatchWork());
-        e = launch_gs_batch(G.fp32, G.ha, G.hf, G.items, *w, s);
+        const hipError_t e = launch_gs_batch(G.fp32, G.ha, G.hf, G.items, *w, s);
         if (e != hipSuccess) {
             for (Job *j : G.jobs) failed->push_back(j);
-            e = hipSuccess;
             continue;
         }
         for (size_t i = 0; i < G.jobs.size(); ++i) {
             Job *j = G.jobs[i];
+            gs_ran->push_back(j);
             j->sweeps_done += G.n[i];
             if (j->sweeps_done >= j->spec.sweeps) j->ph = PH_FINISH;
         }
@@ -356,6 +361,7 @@ hipError_t run_iteration(smooth_ctx *c, const std::vector<Job *> &act, int64_t b
     for (Job *j : act) {
         if (j->ph != PH_FINISH) continue;
         if (std::find(failed->begin(), failed->end(), j) != failed->end()) continue;
+        hipError_t e = hipSuccess;
         if (j->refined && j->spec.sweeps > 0) {
             const float *res = (!j->gs && j->parity) ? j->s32 : j->e32;
             e = launch_correct(j->g, j->u, res, true, s);
@@ -365,7 +371,6 @@ hipError_t run_iteration(smooth_ctx *c, const std::vector<Job *> &act, int64_t b
         if (e == hipSuccess) e = hipEventRecord(j->ev_done, s);
         if (e != hipSuccess) {
             failed->push_back(j);
-            e = hipSuccess;
             continue;
         }
         j->ph = PH_DOWNLOADING;
@@ -389,10 +394,19 @@ void scheduler(smooth_ctx *c) {
         }
         const int64_t batch = c->batches++;
         lk.unlock();
-        std::vector<Job *> completed, failed;
-        (void)run_iteration(c, act, batch, &completed, &failed);
+        std::vector<Job *> completed, failed, gs_ran;
+        (void)run_iteration(c, act, batch, &completed, &failed, &gs_ran);
         hipError_t e = hipEventRecord(c->ev_iter, c->s_comp);
         if (e == hipSuccess) e = hipEventSynchronize(c->ev_iter);
+        if (e == hipSuccess && !gs_ran.empty()) {
+            // a wavefront batch that gave up waiting leaves partial results
+            uint32_t st = 0;
+            e = gs_status(c->cfg.device, c->s_comp, true, &st);
+            if (e == hipSuccess && (st & 1u)) {
+                set_error("job iteration: a Gauss-Seidel wavefront gave up waiting");
+                for (Job *j : gs_ran) failed.push_back(j);
+            }
+        }
         lk.lock();
         if (e != hipSuccess) {
             set_error(std::string("job iteration: ") + hipGetErrorString(e));
@@ -402,7 +416,8 @@ void scheduler(smooth_ctx *c) {
         }
         for (Job *j : failed)
             if (j->ph != PH_END) finish(c, j, SMOOTH_FAILED);
-        for (Job *j : completed) c->to_download.push_back(j);
+        for (Job *j : completed)
+            if (j->ph != PH_END) c->to_download.push_back(j);
         if (!completed.empty()) c->cv_io.notify_all();
     }
     c->sched_done = true;

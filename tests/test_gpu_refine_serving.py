@@ -69,6 +69,28 @@ def test_refine_fp32_inner_fixed_steps(P, olib, method):
 
 
 @pytest.mark.parametrize("method", [0, 1, 2])
+def test_refine_fp32_inner_fixed_steps_192(P, olib, method):
+    """Two defect-correction steps on 192^3 (the float inner passes run
+    interior tiles of the fused pass and the full wavefront), bit-exact
+    against the oracle's loop."""
+    n = 192
+    u0, fp = _poisson((n, n, n), seed=8)
+    m = 16
+    assert P.jacobi_tiles(u0.shape, 6, fp32=True, rhs=True)[3] >= 1
+    say("refine 192^3 fp32 inner method=%d (oracle)" % method)
+    ref, rc, outer, rel = oracle.refine(u0, fp, method=method, inner_f32=True, m=m, tol=0.0,
+                                        max_outer=2, lib=olib)
+    du = to_dev(u0)
+    say("refine 192^3 fp32 inner method=%d (GPU)" % method)
+    od, grel, grc = P.refine_solve(du, to_dev(fp), method=method, inner_fp32=True,
+                                   inner_sweeps=m, rel_tol=0.0, max_outer=2,
+                                   raise_on_noconv=False)
+    assert grc == -6 and od == 2 and rc == -6 and outer == 2
+    assert_same(to_host(du), ref, "refine 192^3 fp32 inner method=%d" % method)
+    assert abs(grel - rel) <= 1e-12 * rel
+
+
+@pytest.mark.parametrize("method", [0, 1, 2])
 def test_refine_plain_fp64_fixed_steps(P, olib, method):
     """The plain FP64 method: m sweeps of the smoother with f' between checks."""
     u0, fp = _poisson((18, 11, 16), seed=5)
@@ -212,3 +234,30 @@ def test_service_shutdown_cancels_pending(P, olib):
         else:
             assert_same(o, oracle.gauss_seidel(u, 3, lib=olib), "job done before shutdown")
     assert cancelled >= 1
+
+
+def test_service_large_jobs_alone_mixed_oracle(P, olib):
+    """Jobs of 130^3 and more (their passes run interior tiles of the batched
+    kernels) next to small ones: each result is the same alone and in the mix,
+    FP64 jobs equal the oracle bit for bit, FP32-refined jobs equal the
+    oracle's emulation of the same steps and the plain result within 1e-5."""
+    specs = [((140, 136, 132), 0, 0, 9), ((131, 150, 133), 1, 1, 7),
+             ((133, 131, 140), 0, 1, 8), ((136, 140, 131), 1, 0, 5)]
+    jobs = []
+    for k, (dims, method, prec, sweeps) in enumerate(specs):
+        jobs.append(dict(u=si.uniform_padded(*dims, 1, seed=500 + k), method=method, prec=prec,
+                         sweeps=sweeps, a=0.0, b=1.0 / 6.0))
+    jobs += _jobs(seed=9, n=6)
+    say("service: %d jobs incl. four of >= 130^3" % len(jobs))
+    mixed, states, info = _serve(P, jobs, 1 << 30, max_inflight=10)
+    assert info.max_resident_seen >= 2
+    for k, j in enumerate(jobs):
+        assert states[k][0] == P.SmoothService.DONE, k
+        assert_same(mixed[k], _expected(j, olib), "large-mix job %d vs oracle" % k)
+        if j["prec"] == 1 and j["sweeps"] > 0:
+            plain = oracle.smooth(j["method"], j["u"], j["sweeps"], a=j["a"], b=j["b"], lib=olib)
+            assert np.abs(mixed[k] - plain).max() <= 1e-5 * max(1.0, np.abs(plain).max())
+    for k in range(len(specs)):
+        alone, st, _ = _serve(P, [jobs[k]], 1 << 30, max_inflight=1)
+        assert st[0][0] == P.SmoothService.DONE
+        assert_same(alone[0], mixed[k], "large job %d alone vs mixed" % k)
