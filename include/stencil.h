@@ -156,6 +156,28 @@ int stencil_gs(const st_grid *grid, int32_t dtype, void *u, const void *f, const
                int32_t bc, double bc_value, int32_t sweeps, int32_t t_fuse, void *hip_stream);
 
 /*
+ * stencil_gs_noalloc -- stencil_gs for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same sweeps, arguments, result bits and bounded
+ * waits, but no hipMalloc, hipMallocAsync, hipFree or other allocating call.
+ * The wavefront workspace (progress counters, ticket, item table) lives in a
+ * static device array of 4 MiB that the library holds on every device it
+ * runs on until the process ends.  Each launch clears what it uses, so no
+ * state carries over between calls; calls that overlap on one device (on
+ * different streams, or from different threads) race for the array and must
+ * not be issued.  One launch needs about 8 bytes per (sweep, 8x8 bundle of
+ * x-lines); sweeps in flight per launch (t_fuse, 0 = as many as possible)
+ * are capped so that a launch fits the array, which changes only the
+ * schedule, never the result.  ST_EINVAL, before anything is enqueued, when
+ * even one sweep does not fit (ceil(ny/8) * ceil(nz/8) above about 520,000
+ * bundles, e.g. ny = nz = 6000), and for every argument stencil_gs rejects.
+ * The caller owns u and f as for stencil_gs.
+ */
+int stencil_gs_noalloc(const st_grid *grid, int32_t dtype, void *u, const void *f,
+                       const st_weights *w, int32_t bc, double bc_value, int32_t sweeps,
+                       int32_t t_fuse, void *hip_stream);
+
+/*
  * Bounded waits of the Gauss-Seidel wavefront.  A wave of the wavefront
  * kernel waits (spins) on its neighbours' progress counters.  Every such
  * wait is bounded: after `polls` polls (stencil_gs_spin_limit; default 2^24,
@@ -243,6 +265,7 @@ int stencil_refine_solve(const st_grid *grid, int32_t method, int32_t inner_dtyp
                          const double *fp, int32_t inner_sweeps, int32_t t_fuse, double rel_tol,
                          int32_t max_outer, int32_t *outer_done, double *rel_res_out,
                          void *hip_stream);
+
 
 /* ------------------------------------------------------------------------
  * Continuous-batching job service.  Jobs (independent smoothing problems of

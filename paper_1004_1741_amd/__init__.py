@@ -82,6 +82,8 @@ SIGNATURES = [
     ("stencil_jacobi_tiles", _i32, [_P(Grid), _i32, _i32, _i32, _P(_i32), _P(_i32), _P(_i32),
                                     _P(_i32)]),
     ("stencil_gs", _i32, [_P(Grid), _i32, _vp, _vp, _P(Weights), _i32, _dbl, _i32, _i32, _vp]),
+    ("stencil_gs_noalloc", _i32,
+     [_P(Grid), _i32, _vp, _vp, _P(Weights), _i32, _dbl, _i32, _i32, _vp]),
     ("stencil_sync", _i32, [_vp]),
     ("stencil_gs_abort", _i32, [_i32]),
     ("stencil_gs_spin_limit", _i32, [_i64]),
@@ -227,6 +229,19 @@ def gauss_seidel(u, sweeps, a=0.0, b=1.0 / 6.0, f=None, g=0.0, t_fuse=0, halo=1,
     _check(lib().stencil_gs(ctypes.byref(grid), _dtype_code(u), _dev_ptr(u, "u"), _dev_ptr(f, "f"),
                             ctypes.byref(w), bc, bc_value, int(sweeps), int(t_fuse),
                             _stream(stream)))
+    return u
+
+
+def gauss_seidel_noalloc(u, sweeps, a=0.0, b=1.0 / 6.0, f=None, g=0.0, t_fuse=0, halo=1,
+                         bc=ST.BC_KEEP, bc_value=0.0, stream=None):
+    """gauss_seidel through the allocation-free entry point (workspace in the
+    library's static device array; calls must not overlap on one device)."""
+    _check_rhs(u, f, halo)
+    grid = _dims(u, halo)
+    w = Weights(a, b, g)
+    _check(lib().stencil_gs_noalloc(ctypes.byref(grid), _dtype_code(u), _dev_ptr(u, "u"),
+                                    _dev_ptr(f, "f"), ctypes.byref(w), bc, bc_value, int(sweeps),
+                                    int(t_fuse), _stream(stream)))
     return u
 
 

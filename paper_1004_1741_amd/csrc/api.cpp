@@ -165,6 +165,20 @@ int run_gs(const Geom &g, bool fp32, void *u, const void *f, double a, double b,
     return ST_OK;
 }
 
+// The same launches with the workspace in the library's static device array:
+// sweeps per launch are capped so that one launch's workspace fits it.
+int run_gs_noalloc(const Geom &g, bool fp32, void *u, const void *f, double a, double b,
+                   double gw, int sweeps, int t_fuse, hipStream_t s) {
+    int per = t_fuse == 0 ? 4095 : t_fuse;
+    if (per > 4095) per = 4095;
+    while (per > 1 && gs_workspace_bytes(per, g.ny, g.nz) > GS_NOALLOC_BYTES) --per;
+    for (int done = 0; done < sweeps; done += per) {
+        const int n = sweeps - done < per ? sweeps - done : per;
+        HIP_TRY(launch_gs_noalloc(fp32, g, u, f, a, b, gw, n, s), "gauss-seidel launch");
+    }
+    return ST_OK;
+}
+
 // ST_EHIP (and clears the flag) if a wavefront launch on the current device
 // gave up waiting; synchronizes s.
 int check_gs_status(hipStream_t s) {
@@ -314,6 +328,34 @@ int stencil_gs(const st_grid *grid, int32_t dtype, void *u, const void *f, const
     if (bc == ST_BC_CONST) HIP_TRY(launch_fill_ghosts(fp32, g, u, bc_value, s), "ghost fill");
     if (sweeps == 0) return ST_OK;
     return run_gs(g, fp32, u, f, w->center, w->neighbor, f ? w->rhs : 0.0, sweeps, t_fuse, s);
+}
+
+int stencil_gs_noalloc(const st_grid *grid, int32_t dtype, void *u, const void *f,
+                       const st_weights *w, int32_t bc, double bc_value, int32_t sweeps,
+                       int32_t t_fuse, void *hip_stream) {
+    Geom g;
+    int rc = check_grid(grid, &g);
+    if (rc) return rc;
+    if (dtype != ST_FP64 && dtype != ST_FP32) return fail(ST_EINVAL, "dtype must be FP64 or FP32");
+    if (!u) return fail(ST_EINVAL, "u must be a device pointer");
+    if (!w) return fail(ST_EINVAL, "weights is NULL");
+    if (bc != ST_BC_KEEP && bc != ST_BC_CONST) return fail(ST_EINVAL, "bc must be KEEP or CONST");
+    if (sweeps < 0) return fail(ST_EINVAL, "sweeps must be >= 0");
+    if (!valid_t(t_fuse)) return fail(ST_EINVAL, "t_fuse must be 0..8 or 16");
+    if (g.ny > 8192 || g.nz > 8192)
+        return fail(ST_EINVAL, "Gauss-Seidel supports ny, nz <= 8192");
+    if (gs_workspace_bytes(1, g.ny, g.nz) > GS_NOALLOC_BYTES)
+        return fail(ST_EINVAL, "grid too large for stencil_gs_noalloc: the workspace of one "
+                               "sweep (8 bytes per 8x8 bundle of x-lines) exceeds its 4 MiB "
+                               "static device array; use stencil_gs");
+    if (!std::isfinite(w->center) || !std::isfinite(w->neighbor) || !std::isfinite(w->rhs))
+        return fail(ST_EINVAL, "weights must be finite");
+    const bool fp32 = dtype == ST_FP32;
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (bc == ST_BC_CONST) HIP_TRY(launch_fill_ghosts(fp32, g, u, bc_value, s), "ghost fill");
+    if (sweeps == 0) return ST_OK;
+    return run_gs_noalloc(g, fp32, u, f, w->center, w->neighbor, f ? w->rhs : 0.0, sweeps,
+                          t_fuse, s);
 }
 
 int stencil_sync(void *hip_stream) { return check_gs_status((hipStream_t)hip_stream); }

@@ -796,6 +796,52 @@ hipError_t launch_gs(bool fp32, const Geom &g, void *u, const void *f, double a,
     return e != hipSuccess ? e : ef;
 }
 
+// ---- allocation-free variant: workspace in a static device array ----
+// One array per device, held until the process ends.  Host code never uses
+// the array's name as an address: the device address comes from
+// hipGetSymbolAddress, looked up once per device with that device current.
+// Every launch rebuilds its item table and clears its counters and ticket in
+// this array (gs_prefix_kernel, gs_items_kernel), so nothing carries over
+// from the previous call; calls that overlap on one device race for it.
+static __device__ __align__(256) unsigned char scratch[GS_NOALLOC_BYTES];
+
+static unsigned char *g_scratch_ptr[64];  // device address of scratch, per device
+
+static hipError_t device_scratch(int dev, unsigned char **out) {
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_ctl_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = static_cast<unsigned char *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+size_t gs_workspace_bytes(int sweeps, int ny, int nz) {
+    return gs_work_layout(sweeps, (ny + 7) / 8, (nz + 7) / 8, nullptr).bytes;
+}
+
+hipError_t launch_gs_noalloc(bool fp32, const Geom &g, void *u, const void *f, double a,
+                             double b, double gw, int sweeps, hipStream_t s) {
+    if (sweeps < 1 || sweeps > 4095) return hipErrorInvalidValue;
+    if (gs_workspace_bytes(sweeps, g.ny, g.nz) > GS_NOALLOC_BYTES) return hipErrorInvalidValue;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    GsCtl *ctl = nullptr;
+    e = device_ctl(dev, s, &ctl);
+    if (e != hipSuccess) return e;
+    unsigned char *ws = nullptr;
+    e = device_scratch(dev, &ws);
+    if (e != hipSuccess) return e;
+    return fp32 ? launch_gs_any<float>(g, u, f, a, b, gw, sweeps, ctl, ws, s)
+                : launch_gs_any<double>(g, u, f, a, b, gw, sweeps, ctl, ws, s);
+}
+
 hipError_t gs_status(int dev, hipStream_t s, bool clear, uint32_t *status) {
     GsCtl *ctl = nullptr;
     hipError_t e = device_ctl(dev, s, &ctl);

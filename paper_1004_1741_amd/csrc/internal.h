@@ -106,6 +106,13 @@ hipError_t launch_correct(const Geom &g, double *u, const void *e, bool e_fp32, 
 // hipMallocAsync on s and released with hipFreeAsync after the launch.
 hipError_t launch_gs(bool fp32, const Geom &g, void *u, const void *f, double a, double b,
                      double gw, int sweeps, hipStream_t s);
+// Allocation-free variant: the workspace lives in a static device array of
+// GS_NOALLOC_BYTES per device instead of the stream-ordered allocator.
+// hipErrorInvalidValue when the workspace of `sweeps` does not fit it.
+constexpr size_t GS_NOALLOC_BYTES = (size_t)4 << 20;
+size_t gs_workspace_bytes(int sweeps, int ny, int nz);
+hipError_t launch_gs_noalloc(bool fp32, const Geom &g, void *u, const void *f, double a,
+                             double b, double gw, int sweeps, hipStream_t s);
 // Synchronizes s, then reads (and optionally clears, with the abort word)
 // the device's wavefront status: bit 0 = a launch gave up waiting.
 hipError_t gs_status(int dev, hipStream_t s, bool clear, uint32_t *status);

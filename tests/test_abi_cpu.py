@@ -111,6 +111,22 @@ def test_gs_validation(P, kw):
     assert rc == P.ST.EINVAL
 
 
+@pytest.mark.parametrize("kw", [dict(nz=0), dict(dtype=2), dict(u=None), dict(t=11),
+                                dict(sweeps=-3), dict(ny=9000), dict(ny=6000, nz=6000)])
+def test_gs_noalloc_validation(P, kw):
+    """The allocation-free entry point rejects what stencil_gs rejects, and a
+    grid whose one-sweep workspace exceeds its static device array, before
+    any device call."""
+    L = P.lib()
+    g = _grid(P, ny=kw.get("ny", 8), nz=kw.get("nz", 8))
+    w = P.Weights(0.0, 1.0 / 6.0, 0.0)
+    rc = L.stencil_gs_noalloc(ctypes.byref(g), kw.get("dtype", 0), kw.get("u", FAKE), None,
+                              ctypes.byref(w), 0, 0.0, kw.get("sweeps", 1), kw.get("t", 0), None)
+    assert rc == P.ST.EINVAL
+    if kw.get("ny") == 6000:
+        assert b"4 MiB" in L.stencil_last_error()
+
+
 def test_refine_and_residual_validation(P):
     L = P.lib()
     g = _grid(P)
