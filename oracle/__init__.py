@@ -69,6 +69,23 @@ def _bind(lib):
     lib.oracle_refine.restype = i32
     lib.oracle_refined_job.argtypes = [i64, i64, i64, i64, i32, vp, vp, dbl, dbl, dbl, i32]
     lib.oracle_refined_job.restype = i32
+    for name in ("oracle_mg_restrict_f64", "oracle_mg_restrict_f32"):
+        getattr(lib, name).argtypes = [i64, i64, i64, vp, vp, dbl]
+        getattr(lib, name).restype = None
+    for name in ("oracle_mg_prolong_add_f64", "oracle_mg_prolong_add_f32"):
+        getattr(lib, name).argtypes = [i64, i64, i64, i64, vp, vp]
+        getattr(lib, name).restype = None
+    lib.oracle_mg_residual_f32.argtypes = [i64, i64, i64, i64, vp, vp, vp]
+    lib.oracle_mg_residual_f32.restype = None
+    lib.oracle_mg_levels.argtypes = [i64, i64, i64]
+    lib.oracle_mg_levels.restype = i32
+    lib.oracle_mg_coarse_n.argtypes = [i64]
+    lib.oracle_mg_coarse_n.restype = i64
+    lib.oracle_mg_scale.argtypes = [i64, i64, i64]
+    lib.oracle_mg_scale.restype = dbl
+    lib.oracle_mg_solve.argtypes = [i64, i64, i64, i64, i32, i32, vp, vp, i32, i32, i32, dbl, i32,
+                                    ctypes.POINTER(i32), ctypes.POINTER(dbl), vp]
+    lib.oracle_mg_solve.restype = i32
     return lib
 
 
@@ -185,3 +202,73 @@ def refined_job(method, u, sweeps, a=0.0, b=1.0 / 6.0, f=None, g=0.0, h=1, lib=N
     if rc != 0:
         raise MemoryError("oracle allocation failed")
     return out
+
+
+# --- multigrid (test infrastructure like everything here) -------------------
+
+def mg_coarse_dims(nx, ny, nz):
+    """Interior extents of the next coarser level: floor((n+1)/2) - 1 per axis."""
+    return (nx + 1) // 2 - 1, (ny + 1) // 2 - 1, (nz + 1) // 2 - 1
+
+
+def mg_scale(nx, ny, nz, lib=None):
+    """h/H factor of the restriction from this level to the next (FP64)."""
+    lib = lib or load()
+    return float(lib.oracle_mg_scale(nx, ny, nz))
+
+
+def mg_levels(nx, ny, nz, lib=None):
+    lib = lib or load()
+    return int(lib.oracle_mg_levels(nx, ny, nz))
+
+
+def mg_restrict(res, scale=None, lib=None):
+    """scale * P^T res for an interior-only fine residual (scale defaults to
+    the level's h/H, as in the V-cycle)."""
+    lib = lib or load()
+    dt = np.float32 if np.asarray(res).dtype == np.float32 else np.float64
+    res = np.ascontiguousarray(res, dtype=dt)
+    fnz, fny, fnx = res.shape
+    cnx, cny, cnz = mg_coarse_dims(fnx, fny, fnz)
+    if scale is None:
+        scale = mg_scale(fnx, fny, fnz, lib)
+    rc = np.zeros((cnz, cny, cnx), dtype=dt)
+    fn = lib.oracle_mg_restrict_f32 if dt == np.float32 else lib.oracle_mg_restrict_f64
+    fn(fnx, fny, fnz, _ptr(res), _ptr(rc), float(scale))
+    return rc
+
+
+def mg_prolong_add(ef, ec, h=1, lib=None):
+    """ef + P ec: trilinear interpolation of the padded coarse correction ec
+    (ghost width 1) added to the padded fine correction ef (ghost width h)."""
+    lib = lib or load()
+    dt = np.float32 if np.asarray(ef).dtype == np.float32 else np.float64
+    out = np.ascontiguousarray(ef, dtype=dt).copy()
+    ec = np.ascontiguousarray(ec, dtype=dt)
+    fnx, fny, fnz = _dims(out, h)
+    if ec.shape != tuple(d + 2 for d in mg_coarse_dims(fnz, fny, fnx)):
+        raise ValueError("coarse grid does not match the fine grid")
+    fn = lib.oracle_mg_prolong_add_f32 if dt == np.float32 else lib.oracle_mg_prolong_add_f64
+    fn(fnx, fny, fnz, h, _ptr(out), _ptr(ec))
+    return out
+
+
+def mg_solve(u, fp, smoother=2, inner_f32=True, pre=2, post=2, coarse=16, tol=1e-10,
+             max_cycles=50, h=1, lib=None):
+    """Multigrid-preconditioned defect correction (see oracle.c); returns
+    (u, status, cycles, rel, history of relative residuals)."""
+    lib = lib or load()
+    out = np.ascontiguousarray(u, dtype=np.float64).copy()
+    fpa = np.ascontiguousarray(fp, dtype=np.float64)
+    nx, ny, nz = _dims(out, h)
+    if fpa.shape != (nz, ny, nx):
+        raise ValueError("fp must be interior-only with shape (nz, ny, nx)")
+    hist = np.full(max_cycles + 1, np.nan)
+    cd = ctypes.c_int(0)
+    rel = ctypes.c_double(0.0)
+    rc = lib.oracle_mg_solve(nx, ny, nz, h, int(smoother), int(bool(inner_f32)), _ptr(out),
+                             _ptr(fpa), int(pre), int(post), int(coarse), float(tol),
+                             int(max_cycles), ctypes.byref(cd), ctypes.byref(rel), _ptr(hist))
+    if rc == -2:
+        raise MemoryError("oracle allocation failed")
+    return out, rc, cd.value, rel.value, hist[:cd.value + 1]

@@ -402,6 +402,164 @@ def pin_red_black_masks(lib):
                                                                lib=lib))
 
 
+# --- multigrid transfers and V-cycle ------------------------------------------
+#
+# Sources of truth: the hat-function definition of trilinear interpolation
+# between the points i/(n+1) and I/(nc+1), evaluated in exact rationals; the
+# full-weighting stencil (1/64)[1 2 1]^3 of nested grids; the transpose
+# relation R = scale * P^T; the h^2 scaling (R applied to a constant gives
+# (H/h)^2); and multigrid theory: a V(2,2)-cycle with a smoothing iteration on
+# the 7-point Poisson matrix contracts the residual by a factor well below 1
+# that does not grow with n, and the converged iterate is the exact discrete
+# solution (manufactured from a random u*).
+
+
+def _hat(i, n, I, nc):
+    """Exact hat function of coarse point I at fine point i: max(0, 1 - |X - I|),
+    X = i (nc+1)/(n+1)."""
+    X = Fraction(i * (nc + 1), n + 1)
+    return max(Fraction(0), 1 - abs(X - I))
+
+
+def pin_mg_levels(lib):
+    ns = [512]
+    while len(ns) < 12 and ns[-1] >= 3:
+        ns.append(int(lib.oracle_mg_coarse_n(ns[-1])))
+    assert ns == [512, 255, 127, 63, 31, 15, 7, 3, 1], ns
+    assert lib.oracle_mg_levels(512, 512, 512) == 9
+    assert lib.oracle_mg_levels(2, 40, 40) == 1
+    assert lib.oracle_mg_levels(7, 16, 3) == 2
+    # h/H: 256/513 for 512 (non-nested), exactly 1/2 for nested levels
+    assert lib.oracle_mg_scale(512, 512, 512) == 256.0 / 513.0
+    assert lib.oracle_mg_scale(255, 255, 255) == 0.5
+
+
+def pin_mg_prolong_hat(lib):
+    """P e_c for a coarse delta is the tensor product of exact hat functions
+    (nested: exactly; non-nested: within the rounding of three weights)."""
+    for dims, dt, tol in (((7, 7, 7), np.float64, 0.0), ((10, 8, 12), np.float64, 4 * EPS64),
+                          ((9, 11, 8), np.float32, 4 * EPS32), ((15, 7, 11), np.float32, 0.0)):
+        nx, ny, nz = dims
+        cn = oracle.mg_coarse_dims(nx, ny, nz)
+        for (I, J, K) in ((1, 1, 1), (cn[0], cn[1], cn[2]), ((cn[0] + 1) // 2, 1, cn[2])):
+            ec = np.zeros((cn[2] + 2, cn[1] + 2, cn[0] + 2), dtype=dt)
+            ec[K, J, I] = 1.0
+            ef = np.zeros((nz + 2, ny + 2, nx + 2), dtype=dt)
+            out = oracle.mg_prolong_add(ef, ec, lib=lib)
+            for k in range(1, nz + 1):
+                hz = _hat(k, nz, K, cn[2])
+                for j in range(1, ny + 1):
+                    hy = _hat(j, ny, J, cn[1])
+                    for i in range(1, nx + 1):
+                        ex = _hat(i, nx, I, cn[0]) * hy * hz
+                        got = Fraction(float(out[k, j, i]))
+                        assert abs(got - ex) <= tol * max(ex, Fraction(1, 2 ** 40)) + (
+                            0 if tol == 0 else Fraction(1, 2 ** 100)), (dims, dt, (I, J, K), (k, j, i))
+            assert np.all(out[0] == 0) and np.all(out[:, :, 0] == 0)  # ghosts untouched
+
+
+def pin_mg_full_weighting(lib):
+    """Nested levels: restriction = 4 * (1/64) [1 2 1] x [1 2 1] x [1 2 1]
+    around fine point 2I; bit-exact on small integer data (every partial sum
+    is exact), FP64 and float."""
+    rng = np.random.default_rng(7)
+    for dims in ((7, 7, 7), (15, 7, 3), (11, 15, 7)):
+        nx, ny, nz = dims
+        for dt in (np.float64, np.float32):
+            res = rng.integers(-40, 41, size=(nz, ny, nx)).astype(dt)
+            rc = oracle.mg_restrict(res, lib=lib)
+            pad = np.zeros((nz + 2, ny + 2, nx + 2), dtype=np.int64)
+            pad[1:-1, 1:-1, 1:-1] = res.astype(np.int64)
+            cn = oracle.mg_coarse_dims(nx, ny, nz)
+            w = (1, 2, 1)
+            for K in range(1, cn[2] + 1):
+                for J in range(1, cn[1] + 1):
+                    for I in range(1, cn[0] + 1):
+                        acc = 0
+                        for c in range(3):
+                            for b in range(3):
+                                for a in range(3):
+                                    acc += w[a] * w[b] * w[c] * pad[2 * K + c - 1, 2 * J + b - 1,
+                                                                     2 * I + a - 1]
+                        assert Fraction(float(rc[K - 1, J - 1, I - 1])) == Fraction(acc, 16), (
+                            dims, dt, (I, J, K))
+
+
+def pin_mg_transpose_and_scale(lib):
+    """<R r, e_c> = scale <r, P e_c> for random r, e_c (non-nested, non-cubic),
+    and R applied to a constant gives (H/h)^2 at coarse points whose support
+    stays inside the grid."""
+    rng = np.random.default_rng(11)
+    for dims in ((12, 10, 9), (16, 16, 16), (15, 9, 20)):
+        nx, ny, nz = dims
+        cn = oracle.mg_coarse_dims(nx, ny, nz)
+        r = rng.standard_normal((nz, ny, nx))
+        ec = np.zeros((cn[2] + 2, cn[1] + 2, cn[0] + 2))
+        ec[1:-1, 1:-1, 1:-1] = rng.standard_normal((cn[2], cn[1], cn[0]))
+        scale = oracle.mg_scale(nx, ny, nz, lib=lib)
+        lhs = float(np.sum(oracle.mg_restrict(r, lib=lib) * ec[1:-1, 1:-1, 1:-1]))
+        pe = oracle.mg_prolong_add(np.zeros((nz + 2, ny + 2, nx + 2)), ec, lib=lib)
+        rhs = scale * float(np.sum(r * pe[1:-1, 1:-1, 1:-1]))
+        assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + np.sqrt(r.size)), (dims, lhs, rhs)
+    # nested: a constant restricts to exactly (H/h)^2 = 4 away from the boundary
+    rc = oracle.mg_restrict(np.ones((15, 15, 15)), lib=lib)
+    assert np.all(rc[1:-1, 1:-1, 1:-1] == 4.0), rc[2, 2, 2]
+    # non-nested: scale times the product of the exact hat sums of each axis
+    n = 16
+    nc = oracle.mg_coarse_dims(n, n, n)[0]
+    rc = oracle.mg_restrict(np.ones((n, n, n)), lib=lib)
+    scale = Fraction(nc + 1, n + 1)
+    hs = [sum(_hat(i, n, I, nc) for i in range(1, n + 1)) for I in range(1, nc + 1)]
+    for K in range(nc):
+        for J in range(nc):
+            for I in range(nc):
+                want = float(scale * hs[I] * hs[J] * hs[K])
+                assert abs(rc[K, J, I] - want) <= 1e-14 * want, ((I, J, K), rc[K, J, I], want)
+
+
+def _apply_A(u):
+    """(6c - s) at interior sites of a padded grid with ghost width 1."""
+    c = u[1:-1, 1:-1, 1:-1]
+    s = (u[1:-1, 1:-1, :-2] + u[1:-1, 1:-1, 2:] + u[1:-1, :-2, 1:-1] + u[1:-1, 2:, 1:-1] +
+         u[:-2, 1:-1, 1:-1] + u[2:, 1:-1, 1:-1])
+    return 6.0 * c - s
+
+
+def pin_mg_convergence(lib):
+    """V(2,2) contracts the residual by <= 0.35 per cycle for every smoother,
+    at n = 8 and 16 alike (no growth with n), and reaches 1e-10."""
+    rng = np.random.default_rng(3)
+    for n in (8, 16, 15):
+        fp = (2 * rng.random((n, n, n)) - 1) / (n + 1) ** 2
+        u0 = np.zeros((n + 2,) * 3)
+        for sm in (0, 1, 2):
+            out, rc, cyc, rel, hist = oracle.mg_solve(u0, fp, smoother=sm, inner_f32=False,
+                                                      pre=2, post=2, coarse=16, tol=1e-10,
+                                                      max_cycles=30, lib=lib)
+            assert rc == 0 and rel <= 1e-10, (n, sm, rc, rel)
+            fac = (hist[-1] / hist[1]) ** (1.0 / (len(hist) - 2))
+            assert fac <= 0.35, (n, sm, fac)
+
+
+def pin_mg_manufactured(lib):
+    """The FP32-inner V-cycle defect correction converges to the exact
+    discrete solution u* of A u* = f' (f' manufactured from a random u*)."""
+    rng = np.random.default_rng(5)
+    for dims in ((12, 9, 10), (15, 15, 15)):
+        nx, ny, nz = dims
+        us = np.zeros((nz + 2, ny + 2, nx + 2))
+        us[1:-1, 1:-1, 1:-1] = rng.random((nz, ny, nx))
+        fp = _apply_A(us)
+        for sm, most in ((0, 32), (2, 20)):
+            out, rc, cyc, rel, _ = oracle.mg_solve(np.zeros_like(us), fp, smoother=sm,
+                                                   inner_f32=True, tol=1e-13, max_cycles=60,
+                                                   lib=lib)
+            assert rc == 0 and cyc <= most, (dims, sm, rel, cyc)  # float V-cycles contract too
+            assert np.max(np.abs(out - us)) <= 1e-10, (dims, sm, np.max(np.abs(out - us)))
+
+
 ALL_PINS = [pin_operand_order, pin_jacobi_sine_decay, pin_fixed_points, pin_exact_rational, pin_exact_rational_f32,
             pin_gs_rate, pin_gs_differs_from_jacobi, pin_residual_mode, pin_defect_correction,
-            pin_manufactured_solution, pin_split_invariance, pin_red_black_masks]
+            pin_manufactured_solution, pin_split_invariance, pin_red_black_masks, pin_mg_levels,
+            pin_mg_prolong_hat, pin_mg_full_weighting, pin_mg_transpose_and_scale,
+            pin_mg_convergence, pin_mg_manufactured]

@@ -63,6 +63,23 @@ MUTATIONS = [
     ("jacobi_f32_update_in_double", "oracle_jacobi_f32",
      "v = (a * src[IDX(k, j, i)]) + (b * s);",
      "v = (float)(((double)a * src[IDX(k, j, i)]) + ((double)b * s));"),
+    # multigrid
+    ("mg_restrict_no_scale", "oracle_mg_restrict_f64",
+     "= zs * scale;", "= zs;"),
+    ("mg_prolong_swapped_weights", "oracle_mg_prolong_add_f64",
+     "vx[b] = (wmx * row[I0]) + (wqx * row[I0 + 1]);",
+     "vx[b] = (wqx * row[I0]) + (wmx * row[I0 + 1]);"),
+    ("mg_restrict_y_weights_of_x", "oracle_mg_restrict_f64",
+     "ys = ys + (mg_w64(j, J, fny, cny) * xs);", "ys = ys + (mg_w64(j, J, fnx, cnx) * xs);"),
+    ("mg_restrict_f32_centre_weight", "oracle_mg_restrict_f32",
+     "zs = zs + (mg_w32(k, K, fnz, cnz) * ys);", "zs = zs + ys;"),
+    ("mg_prolong_f32_z_lo_only", "oracle_mg_prolong_add_f32",
+     "const float v = (wmz * vy[0]) + (wqz * vy[1]);", "const float v = vy[0];"),
+    ("mg_residual_f32_sign", "oracle_mg_residual_f32",
+     "res[FIDX(k, j, i)] = fp[FIDX(k, j, i)] - ((6.0f * c) - s);",
+     "res[FIDX(k, j, i)] = fp[FIDX(k, j, i)] + ((6.0f * c) - s);"),
+    ("mg_coarse_support_short", "mg_support",
+     "*hi = ((I + 1) * (n + 1) - 1) / (nc + 1);", "*hi = (I * (n + 1)) / (nc + 1);"),
 ]
 
 
