@@ -266,6 +266,43 @@ int stencil_refine_solve(const st_grid *grid, int32_t method, int32_t inner_dtyp
                          int32_t max_outer, int32_t *outer_done, double *rel_res_out,
                          void *hip_stream);
 
+/*
+ * stencil_mg_solve -- solve the h^2-scaled Poisson system A u = f' with
+ * multigrid V-cycles whose smoother is one of this library's sweeps (the
+ * paper names multigrid as the main user of these smoothers, Sec. 1), inside
+ * the same FP64 defect correction as stencil_refine_solve:
+ *     loop: r = f' - A u (FP64, deterministic norm); stop when
+ *           ||r|| / ||f'|| <= rel_tol;  e = one V-cycle on A e = r in the
+ *           inner precision (FP32: r rounded to float, every level in
+ *           float);  u = u + e (FP64).
+ *  Levels: the grid, then floor((n+1)/2) - 1 points per axis while every axis
+ *  has >= 3 (512 -> 255 -> 127 -> ... -> 1).  Transfers: trilinear
+ *  interpolation P between the level's points x_i = i/(n+1) and the coarse
+ *  points X_I = I/(nc+1) (the nested full-weighting pair when n+1 is even);
+ *  restriction = (h/H) P^T, i.e. the coarse right-hand side of the
+ *  H^2-scaled coarse system.  V-cycle: e = 0, `pre` sweeps, restrict the
+ *  residual, V-cycle one level down, e += P e_coarse, `post` sweeps; the
+ *  coarsest level runs `coarse_sweeps` sweeps.
+ *  smoother: 0 = weighted Jacobi, omega = 6/7 (weights a = b = g = 1/7, the
+ *            fused Jacobi pass), 1 = lexicographic Gauss-Seidel (the
+ *            wavefront), 2 = red-black Gauss-Seidel (the fused red-black pass);
+ *            a = 0, b = g = 1/6 for 1 and 2.
+ *  inner_dtype: ST_FP32 or ST_FP64.  u: FP64 padded grid (ghost width
+ *  grid->halo, Dirichlet values in its ghosts are used by the FP64 residual;
+ *  corrections have zero ghosts); fp: FP64 interior-only right-hand side.
+ *  Synchronous.  *cycles_done = V-cycles applied, *rel_res_out = last
+ *  relative residual (either may be NULL).  Returns ST_OK on convergence,
+ *  ST_ENOCONV after max_cycles V-cycles; ST_EINVAL for smoother outside 0..2,
+ *  pre/post outside 0..64, coarse_sweeps outside 1..4096, max_cycles < 0,
+ *  rel_tol < 0 or NaN, NULL u/fp, and the grid conditions of stencil_jacobi;
+ *  ST_EHIP on a device error or a Gauss-Seidel wavefront that gave up.  The
+ *  library allocates one workspace (about 2.3x the grid in the inner
+ *  precision) per call and frees it before returning.
+ */
+int stencil_mg_solve(const st_grid *grid, int32_t smoother, int32_t inner_dtype, double *u,
+                     const double *fp, int32_t pre, int32_t post, int32_t coarse_sweeps,
+                     double rel_tol, int32_t max_cycles, int32_t *cycles_done,
+                     double *rel_res_out, void *hip_stream);
 
 /* ------------------------------------------------------------------------
  * Continuous-batching job service.  Jobs (independent smoothing problems of

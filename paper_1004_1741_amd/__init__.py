@@ -91,6 +91,8 @@ SIGNATURES = [
     ("stencil_residual", _i32, [_P(Grid), _vp, _vp, _vp, _P(_dbl), _vp]),
     ("stencil_refine_solve", _i32, [_P(Grid), _i32, _i32, _vp, _vp, _i32, _i32, _dbl, _i32,
                                     _P(_i32), _P(_dbl), _vp]),
+    ("stencil_mg_solve", _i32, [_P(Grid), _i32, _i32, _vp, _vp, _i32, _i32, _i32, _dbl, _i32,
+                                _P(_i32), _P(_dbl), _vp]),
     ("smooth_init", _i32, [_P(SmoothConfig), _P(_vp)]),
     ("smooth_submit", _i32, [_vp, _P(SmoothJob), _P(_u64)]),
     ("smooth_poll", _i32, [_vp, _u64, _P(_i32), _P(SmoothStats)]),
@@ -313,6 +315,30 @@ def refine_solve(u, fp, method=0, inner_fp32=True, inner_sweeps=16, t_fuse=0, re
     if rc != 0 and not (rc == ST.ENOCONV and not raise_on_noconv):
         _check(rc)
     return od.value, rel.value, rc
+
+
+def mg_solve(u, fp, smoother=2, inner_fp32=True, pre=2, post=2, coarse_sweeps=16,
+             rel_tol=1e-10, max_cycles=100, halo=1, stream=None, raise_on_noconv=True):
+    """Solve A u = f' by FP64 defect correction around one multigrid V-cycle
+    per step (FP32 or FP64), with weighted Jacobi (0), Gauss-Seidel (1) or
+    red-black Gauss-Seidel (2) as the smoother.
+
+    Returns (cycles, relative_residual, status)."""
+    _check_fp64_grid(u)
+    if fp is None:
+        raise ValueError("fp is required")
+    _check_fp64_interior(u, fp, "fp", halo)
+    grid = _dims(u, halo)
+    cd = ctypes.c_int32(0)
+    rel = ctypes.c_double(0.0)
+    rc = lib().stencil_mg_solve(ctypes.byref(grid), int(smoother),
+                                ST.FP32 if inner_fp32 else ST.FP64, _dev_ptr(u, "u"),
+                                _dev_ptr(fp, "fp"), int(pre), int(post), int(coarse_sweeps),
+                                float(rel_tol), int(max_cycles), ctypes.byref(cd),
+                                ctypes.byref(rel), _stream(stream))
+    if rc != 0 and not (rc == ST.ENOCONV and not raise_on_noconv):
+        _check(rc)
+    return cd.value, rel.value, rc
 
 
 class SmoothService:

@@ -501,4 +501,153 @@ int stencil_refine_solve(const st_grid *grid, int32_t method, int32_t inner_dtyp
     return status;
 }
 
+int stencil_mg_solve(const st_grid *grid, int32_t smoother, int32_t inner_dtype, double *u,
+                     const double *fp, int32_t pre, int32_t post, int32_t coarse_sweeps,
+                     double rel_tol, int32_t max_cycles, int32_t *cycles_done,
+                     double *rel_res_out, void *hip_stream) {
+    Geom g;
+    int rc = check_grid(grid, &g);
+    if (rc) return rc;
+    if (smoother < 0 || smoother > 2)
+        return fail(ST_EINVAL, "smoother must be 0 (weighted Jacobi), 1 (GS) or 2 (red-black GS)");
+    if (inner_dtype != ST_FP64 && inner_dtype != ST_FP32)
+        return fail(ST_EINVAL, "inner_dtype must be FP64 or FP32");
+    if (!u || !fp) return fail(ST_EINVAL, "u and fp must be device pointers");
+    if (pre < 0 || post < 0 || pre > 64 || post > 64)
+        return fail(ST_EINVAL, "pre and post must be 0..64");
+    if (coarse_sweeps < 1 || coarse_sweeps > 4096)
+        return fail(ST_EINVAL, "coarse_sweeps must be 1..4096");
+    if (max_cycles < 0) return fail(ST_EINVAL, "max_cycles must be >= 0");
+    if (!(rel_tol >= 0.0)) return fail(ST_EINVAL, "rel_tol must be >= 0");
+    if (smoother == 1 && (g.ny > 8192 || g.nz > 8192))
+        return fail(ST_EINVAL, "Gauss-Seidel supports ny, nz <= 8192");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const bool f32 = inner_dtype == ST_FP32;
+    const size_t es = f32 ? sizeof(float) : sizeof(double);
+
+    // levels: the grid itself, then floor((n+1)/2) - 1 points per axis while
+    // every axis has >= 3
+    std::vector<Geom> lv(1, g);
+    while (lv.back().nx >= 3 && lv.back().ny >= 3 && lv.back().nz >= 3 && lv.size() < 32) {
+        Geom c;
+        c.nx = mg_coarse_n(lv.back().nx);
+        c.ny = mg_coarse_n(lv.back().ny);
+        c.nz = mg_coarse_n(lv.back().nz);
+        c.h = 1;
+        c.px = c.nx + 2;
+        c.py = c.ny + 2;
+        c.pz = c.nz + 2;
+        lv.push_back(c);
+    }
+    const int nlev = (int)lv.size();
+    // one device allocation: per level e, its Jacobi/red-black scratch, r and
+    // res, then the transfer tables
+    auto up = [](size_t n) { return (n + 255) / 256 * 256; };
+    struct Off { size_t e, es, r, res; };
+    std::vector<Off> off(nlev);
+    size_t total = 0;
+    for (int l = 0; l < nlev; ++l) {
+        off[l].e = total;
+        total += up((size_t)lv[l].count() * es);
+        off[l].es = total;
+        if (smoother != 1) total += up((size_t)lv[l].count() * es);
+        off[l].r = total;
+        total += up((size_t)lv[l].interior() * es);
+        off[l].res = total;
+        total += up((size_t)lv[l].interior() * es);
+    }
+    std::vector<unsigned char> tb;
+    std::vector<MgTables> tabs(nlev > 1 ? nlev - 1 : 0);
+    for (int l = 0; l + 1 < nlev; ++l) mg_build_tables(f32, lv[l], tb, tabs[l]);
+    const size_t tab_off = total;
+    total += up(tb.size());
+    const int nb = residual_partial_count(g);
+    const size_t part_off = total;
+    total += up(((size_t)nb + 2) * sizeof(double));
+    DevBuf work;
+    HIP_TRY(work.alloc(total), "multigrid workspace");
+    unsigned char *base = (unsigned char *)work.p;
+    if (!tb.empty())
+        HIP_TRY(hipMemcpyAsync(base + tab_off, tb.data(), tb.size(), hipMemcpyHostToDevice, s),
+                "multigrid tables");
+    for (auto &t : tabs) t.dev = base + tab_off;
+    auto E = [&](int l) { return (void *)(base + off[l].e); };
+    auto ES = [&](int l) { return (void *)(base + off[l].es); };
+    auto R = [&](int l) { return (void *)(base + off[l].r); };
+    auto RES = [&](int l) { return (void *)(base + off[l].res); };
+    double *partials = (double *)(base + part_off);
+    double *dsum = partials + nb;
+
+    auto smooth = [&](int l, int sweeps) -> int {
+        if (sweeps <= 0) return ST_OK;
+        if (smoother == 0)  // weighted Jacobi, omega = 6/7
+            return run_jacobi(lv[l], f32, E(l), ES(l), R(l), 1.0 / 7.0, 1.0 / 7.0, 1.0 / 7.0,
+                              sweeps, 0, s);
+        if (smoother == 2)
+            return run_rbgs(lv[l], f32, E(l), ES(l), R(l), 0.0, 1.0 / 6.0, 1.0 / 6.0, sweeps, 0,
+                            s);
+        return run_gs(lv[l], f32, E(l), R(l), 0.0, 1.0 / 6.0, 1.0 / 6.0, sweeps, 0, s);
+    };
+    auto zero = [&](int l) {
+        return hipMemsetAsync(E(l), 0, (size_t)lv[l].count() * es, s);
+    };
+    if (smoother != 1)  // scratch ghosts start at 0 (run_jacobi / run_rbgs copy them anyway)
+        for (int l = 0; l < nlev; ++l)
+            HIP_TRY(hipMemsetAsync(ES(l), 0, (size_t)lv[l].count() * es, s), "memset");
+
+    // ||f'|| with the same deterministic reduction as the residual
+    HIP_TRY(launch_residual_poisson(g, nullptr, fp, nullptr, nullptr, partials, nullptr, s),
+            "norm f");
+    HIP_TRY(launch_sum_partials(partials, nb, dsum + 1, s), "norm f");
+    double ff = 0.0;
+    HIP_TRY(hipMemcpyAsync(&ff, dsum + 1, sizeof(double), hipMemcpyDeviceToHost, s), "copy");
+    HIP_TRY(hipStreamSynchronize(s), "sync");
+    const double nf = std::sqrt(ff);
+
+    int cyc = 0, status = ST_ENOCONV;
+    double rel = INFINITY;
+    for (;;) {
+        HIP_TRY(launch_residual_poisson(g, u, fp, f32 ? nullptr : (double *)R(0),
+                                        f32 ? (float *)R(0) : nullptr, partials, nullptr, s),
+                "residual");
+        HIP_TRY(launch_sum_partials(partials, nb, dsum, s), "residual sum");
+        double rr = 0.0;
+        HIP_TRY(hipMemcpyAsync(&rr, dsum, sizeof(double), hipMemcpyDeviceToHost, s), "copy");
+        HIP_TRY(hipStreamSynchronize(s), "sync");
+        rel = nf > 0.0 ? std::sqrt(rr) / nf : std::sqrt(rr);
+        if (rel <= rel_tol) {
+            status = ST_OK;
+            break;
+        }
+        if (cyc >= max_cycles) break;
+        // V-cycle: down (pre-smooth, residual, restrict), coarsest, up
+        // (prolongate, post-smooth)
+        for (int l = 0; l + 1 < nlev; ++l) {
+            HIP_TRY(zero(l), "memset");
+            if ((rc = smooth(l, pre))) return rc;
+            HIP_TRY(launch_mg_residual(f32, lv[l], E(l), R(l), RES(l), s), "mg residual");
+            HIP_TRY(launch_mg_restrict(f32, lv[l], lv[l + 1], tabs[l], RES(l), R(l + 1), s),
+                    "mg restrict");
+        }
+        HIP_TRY(zero(nlev - 1), "memset");
+        if ((rc = smooth(nlev - 1, coarse_sweeps))) return rc;
+        for (int l = nlev - 2; l >= 0; --l) {
+            HIP_TRY(launch_mg_prolong(f32, lv[l], lv[l + 1], tabs[l], E(l), E(l + 1), s),
+                    "mg prolong");
+            if ((rc = smooth(l, post))) return rc;
+        }
+        HIP_TRY(launch_correct(g, u, E(0), f32, s), "correct");
+        ++cyc;
+        if (smoother == 1) {
+            rc = check_gs_status(s);
+            if (rc) return rc;
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(s), "sync");
+    if (cycles_done) *cycles_done = cyc;
+    if (rel_res_out) *rel_res_out = rel;
+    if (status == ST_ENOCONV) set_error("relative residual above rel_tol after max_cycles V-cycles");
+    return status;
+}
+
 }  // extern "C"

@@ -143,6 +143,30 @@ struct GsBatchWork {
 hipError_t launch_gs_batch(bool fp32, bool has_a, bool has_f,
                            const std::vector<GsBatchItem> &items, GsBatchWork &w, hipStream_t s);
 
+// ---- geometric multigrid (mg.hip) ----
+// Next coarser level: floor((n+1)/2) - 1 interior points per axis.
+int mg_coarse_n(int n);
+// h/H factor of the restriction from level g to the next (FP64, host).
+double mg_scale(const Geom &g);
+// Per-axis transfer tables between level `fine` and the next one, in the
+// level's precision: appended to `bytes` (host), offsets in `tab`; the caller
+// copies `bytes` to the device and sets tab.dev.
+struct MgTables {
+    void *dev = nullptr;
+    size_t off_i0[3], off_wm[3], off_wq[3], off_lo[3], off_hi[3];
+};
+void mg_build_tables(bool fp32, const Geom &fine, std::vector<unsigned char> &bytes,
+                     MgTables &tab);
+// res = r - ((6*c) - s) (e padded; r, res interior-only).
+hipError_t launch_mg_residual(bool fp32, const Geom &g, const void *e, const void *r, void *res,
+                              hipStream_t s);
+// rc = scale * P^T res (interior-only; coarse has ghost width 1).
+hipError_t launch_mg_restrict(bool fp32, const Geom &fine, const Geom &coarse,
+                              const MgTables &tab, const void *res, void *rc, hipStream_t s);
+// ef += P ec (both padded).
+hipError_t launch_mg_prolong(bool fp32, const Geom &fine, const Geom &coarse, const MgTables &tab,
+                             void *ef, const void *ec, hipStream_t s);
+
 // Thread-local error message used by the C ABI.
 void set_error(const std::string &msg);
 

@@ -1,0 +1,275 @@
+// mg.hip -- geometric multigrid transfers and the level residual.
+//
+// Multigrid is the solver the smoothers of Sec. 3 exist for (Sec. 1); the
+// V-cycle runs the fused Jacobi pass, the Gauss-Seidel wavefront or the
+// red-black pass as its smoother on every level.  The kernels here are the
+// glue between levels, all elementwise and HBM-bound:
+//
+//   * level residual   res = r - ((6*c) - s)         (precision of the level)
+//   * restriction      r_c = scale * P^T res          (coarse right-hand side)
+//   * prolongation     e_f = e_f + P e_c              (trilinear interpolation)
+//
+// Levels: n interior points per axis at x_i = i/(n+1); the next level has
+// nc = floor((n+1)/2) - 1.  Fine point i sits on the coarse grid at
+// i (nc+1)/(n+1) = I0 + q/(n+1); its interpolation weights are
+// wm = (n+1-q)/(n+1) on I0 and wq = q/(n+1) on I0+1 (one rounded division in
+// the level's precision, coarse ghosts 0).  When n+1 is even this is the
+// nested grid (weights 1, or 1/2 and 1/2; restriction = full weighting);
+// otherwise (n = 512) the coarse spacing is slightly more than twice the fine
+// one and the same formulas interpolate geometrically.  The per-axis tables
+// (I0, wm, wq per fine point; the first and last fine point of every coarse
+// point's support) are computed on the host in the level's precision and
+// read by the kernels; no division happens on the device.
+//
+// Evaluation order (fixed; results are bit-identical from run to run):
+// restriction sums x first (fine i increasing, acc = acc + w * r from 0),
+// then y over those sums, then z, then multiplies by scale; prolongation
+// interpolates along x, then y, then z, each (wm * lo) + (wq * hi).
+#include <cmath>
+#include <cstring>
+
+#include "internal.h"
+
+#pragma clang fp contract(off)
+
+namespace stk {
+namespace {
+
+template <typename T>
+struct MgAxisDev {
+    const int *i0;   // [n + 1]: coarse index I0 of fine point i (entry 0 unused)
+    const T *wm;     // [n + 1]: weight on I0
+    const T *wq;     // [n + 1]: weight on I0 + 1
+    const int *lo;   // [nc + 1]: first fine point with a non-zero weight on I
+    const int *hi;   // [nc + 1]: last such point
+};
+
+template <typename T>
+struct MgArgs {
+    MgAxisDev<T> ax[3];
+    int fnx, fny, fnz, fh;   // fine level interior extents and ghost width
+    int64_t fpx, fplane;     // fine padded pitches
+    int cnx, cny, cnz;       // coarse interior extents (ghost width 1)
+    int64_t cpx, cplane;
+    T scale;
+};
+
+// res = r - ((6*c) - s); e padded (ghost width h), r and res interior-only.
+// One wave per row, four rows per block.
+template <typename T>
+__global__ void __launch_bounds__(256) mg_residual_kernel(const T *__restrict__ e,
+                                                          const T *__restrict__ r,
+                                                          T *__restrict__ res, int nx, int ny,
+                                                          int h, int64_t px, int64_t plane) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int rows_per_plane = (ny + 3) / 4;
+    const int kz = blockIdx.x / rows_per_plane;
+    const int jr = (blockIdx.x - kz * rows_per_plane) * 4 + w;
+    if (jr >= ny) return;
+    const T *c = e + (int64_t)(kz + h) * plane + (int64_t)(jr + h) * px + h;
+    const int64_t fo = ((int64_t)kz * ny + jr) * nx;
+    for (int i = lane; i < nx; i += 64) {
+        T s = c[i - 1];
+        s = s + c[i + 1];
+        s = s + c[i - px];
+        s = s + c[i + px];
+        s = s + c[i - plane];
+        s = s + c[i + plane];
+        res[fo + i] = r[fo + i] - ((T(6) * c[i]) - s);
+    }
+}
+
+// weight of fine point i towards coarse point I on one axis
+template <typename T>
+__device__ __forceinline__ T axis_w(const MgAxisDev<T> &a, int i, int I) {
+    const int i0 = a.i0[i];
+    return I == i0 ? a.wm[i] : (I == i0 + 1 ? a.wq[i] : T(0));
+}
+
+// r_c = scale * P^T res (both interior-only); one wave per coarse row.
+template <typename T>
+__global__ void __launch_bounds__(256) mg_restrict_kernel(MgArgs<T> M,
+                                                          const T *__restrict__ res,
+                                                          T *__restrict__ rc) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int rows_per_plane = (M.cny + 3) / 4;
+    const int K = blockIdx.x / rows_per_plane + 1;
+    const int J = (blockIdx.x - (K - 1) * rows_per_plane) * 4 + w + 1;
+    if (J > M.cny) return;
+    const MgAxisDev<T> &ax = M.ax[0], &ay = M.ax[1], &az = M.ax[2];
+    const int j0 = ay.lo[J], j1 = ay.hi[J], k0 = az.lo[K], k1 = az.hi[K];
+    for (int I = lane + 1; I <= M.cnx; I += 64) {
+        const int i0 = ax.lo[I], i1 = ax.hi[I];
+        T zs = T(0);
+        for (int k = k0; k <= k1; ++k) {
+            T ys = T(0);
+            for (int j = j0; j <= j1; ++j) {
+                const T *row = res + ((int64_t)(k - 1) * M.fny + (j - 1)) * M.fnx;
+                T xs = T(0);
+                for (int i = i0; i <= i1; ++i) xs = xs + (axis_w(ax, i, I) * row[i - 1]);
+                ys = ys + (axis_w(ay, j, J) * xs);
+            }
+            zs = zs + (axis_w(az, k, K) * ys);
+        }
+        rc[((int64_t)(K - 1) * M.cny + (J - 1)) * M.cnx + (I - 1)] = zs * M.scale;
+    }
+}
+
+// e_f += P e_c; e_f padded (ghost width fh), e_c padded (ghost width 1, ghosts
+// 0).  One wave per fine row.
+template <typename T>
+__global__ void __launch_bounds__(256) mg_prolong_kernel(MgArgs<T> M, T *__restrict__ ef,
+                                                         const T *__restrict__ ec) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int rows_per_plane = (M.fny + 3) / 4;
+    const int k = blockIdx.x / rows_per_plane + 1;
+    const int j = (blockIdx.x - (k - 1) * rows_per_plane) * 4 + w + 1;
+    if (j > M.fny) return;
+    const MgAxisDev<T> &ax = M.ax[0], &ay = M.ax[1], &az = M.ax[2];
+    const int J0 = ay.i0[j], K0 = az.i0[k];
+    const T wmy = ay.wm[j], wqy = ay.wq[j], wmz = az.wm[k], wqz = az.wq[k];
+    T *out = ef + (int64_t)(k - 1 + M.fh) * M.fplane + (int64_t)(j - 1 + M.fh) * M.fpx +
+             (M.fh - 1);
+    for (int i = lane + 1; i <= M.fnx; i += 64) {
+        const int I0 = ax.i0[i];
+        const T wmx = ax.wm[i], wqx = ax.wq[i];
+        T vy[2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            T vx[2];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const T *row = ec + (int64_t)(K0 + c) * M.cplane + (int64_t)(J0 + b) * M.cpx;
+                vx[b] = (wmx * row[I0]) + (wqx * row[I0 + 1]);
+            }
+            vy[c] = (wmy * vx[0]) + (wqy * vx[1]);
+        }
+        const T v = (wmz * vy[0]) + (wqz * vy[1]);
+        out[i] = out[i] + v;
+    }
+}
+
+template <typename T>
+MgArgs<T> make_mg_args(const Geom &fine, const Geom &coarse, const MgTables &tab, double scale) {
+    MgArgs<T> M;
+    for (int d = 0; d < 3; ++d) {
+        const unsigned char *b = static_cast<const unsigned char *>(tab.dev);
+        M.ax[d].i0 = reinterpret_cast<const int *>(b + tab.off_i0[d]);
+        M.ax[d].wm = reinterpret_cast<const T *>(b + tab.off_wm[d]);
+        M.ax[d].wq = reinterpret_cast<const T *>(b + tab.off_wq[d]);
+        M.ax[d].lo = reinterpret_cast<const int *>(b + tab.off_lo[d]);
+        M.ax[d].hi = reinterpret_cast<const int *>(b + tab.off_hi[d]);
+    }
+    M.fnx = fine.nx; M.fny = fine.ny; M.fnz = fine.nz; M.fh = fine.h;
+    M.fpx = fine.px; M.fplane = fine.plane();
+    M.cnx = coarse.nx; M.cny = coarse.ny; M.cnz = coarse.nz;
+    M.cpx = coarse.px; M.cplane = coarse.plane();
+    M.scale = (T)scale;
+    return M;
+}
+
+// Host tables of one axis in precision T, appended to `bytes`.
+template <typename T>
+void axis_tables(int n, int nc, std::vector<unsigned char> &bytes, size_t off[5]) {
+    auto put = [&](const void *p, size_t nbytes) {
+        const size_t o = (bytes.size() + 255) / 256 * 256;
+        bytes.resize(o + nbytes);
+        std::memcpy(bytes.data() + o, p, nbytes);
+        return o;
+    };
+    std::vector<int> i0(n + 1, 0), lo(nc + 1, 0), hi(nc + 1, 0);
+    std::vector<T> wm(n + 1, T(0)), wq(n + 1, T(0));
+    for (int i = 1; i <= n; ++i) {
+        const int64_t p = (int64_t)i * (nc + 1);
+        const int64_t a = p / (n + 1), q = p % (n + 1);
+        i0[i] = (int)a;
+        wm[i] = (T)(n + 1 - q) / (T)(n + 1);
+        wq[i] = (T)q / (T)(n + 1);
+    }
+    for (int I = 1; I <= nc; ++I) {
+        int64_t l = ((int64_t)(I - 1) * (n + 1)) / (nc + 1) + 1;
+        int64_t h = ((int64_t)(I + 1) * (n + 1) - 1) / (nc + 1);
+        lo[I] = (int)(l < 1 ? 1 : l);
+        hi[I] = (int)(h > n ? n : h);
+    }
+    off[0] = put(i0.data(), i0.size() * sizeof(int));
+    off[1] = put(wm.data(), wm.size() * sizeof(T));
+    off[2] = put(wq.data(), wq.size() * sizeof(T));
+    off[3] = put(lo.data(), lo.size() * sizeof(int));
+    off[4] = put(hi.data(), hi.size() * sizeof(int));
+}
+
+}  // namespace
+
+int mg_coarse_n(int n) { return (n + 1) / 2 - 1; }
+
+double mg_scale(const Geom &g) {
+    const double rx = (double)(mg_coarse_n(g.nx) + 1) / (double)(g.nx + 1);
+    const double ry = (double)(mg_coarse_n(g.ny) + 1) / (double)(g.ny + 1);
+    const double rz = (double)(mg_coarse_n(g.nz) + 1) / (double)(g.nz + 1);
+    if (rx == ry && ry == rz) return rx;
+    return std::cbrt(rx * ry * rz);
+}
+
+void mg_build_tables(bool fp32, const Geom &fine, std::vector<unsigned char> &bytes,
+                     MgTables &tab) {
+    const int n[3] = {fine.nx, fine.ny, fine.nz};
+    for (int d = 0; d < 3; ++d) {
+        size_t off[5];
+        if (fp32)
+            axis_tables<float>(n[d], mg_coarse_n(n[d]), bytes, off);
+        else
+            axis_tables<double>(n[d], mg_coarse_n(n[d]), bytes, off);
+        tab.off_i0[d] = off[0];
+        tab.off_wm[d] = off[1];
+        tab.off_wq[d] = off[2];
+        tab.off_lo[d] = off[3];
+        tab.off_hi[d] = off[4];
+    }
+}
+
+static unsigned rows_grid(int ny, int nz) { return (unsigned)((int64_t)nz * ((ny + 3) / 4)); }
+
+hipError_t launch_mg_residual(bool fp32, const Geom &g, const void *e, const void *r, void *res,
+                              hipStream_t s) {
+    if (fp32)
+        hipLaunchKernelGGL(mg_residual_kernel<float>, dim3(rows_grid(g.ny, g.nz)), dim3(256), 0, s,
+                           (const float *)e, (const float *)r, (float *)res, g.nx, g.ny, g.h, g.px,
+                           g.plane());
+    else
+        hipLaunchKernelGGL(mg_residual_kernel<double>, dim3(rows_grid(g.ny, g.nz)), dim3(256), 0,
+                           s, (const double *)e, (const double *)r, (double *)res, g.nx, g.ny, g.h,
+                           g.px, g.plane());
+    return hipGetLastError();
+}
+
+hipError_t launch_mg_restrict(bool fp32, const Geom &fine, const Geom &coarse,
+                              const MgTables &tab, const void *res, void *rc, hipStream_t s) {
+    const double scale = mg_scale(fine);
+    const dim3 grid(rows_grid(coarse.ny, coarse.nz));
+    if (fp32)
+        hipLaunchKernelGGL(mg_restrict_kernel<float>, grid, dim3(256), 0, s,
+                           make_mg_args<float>(fine, coarse, tab, scale), (const float *)res,
+                           (float *)rc);
+    else
+        hipLaunchKernelGGL(mg_restrict_kernel<double>, grid, dim3(256), 0, s,
+                           make_mg_args<double>(fine, coarse, tab, scale), (const double *)res,
+                           (double *)rc);
+    return hipGetLastError();
+}
+
+hipError_t launch_mg_prolong(bool fp32, const Geom &fine, const Geom &coarse, const MgTables &tab,
+                             void *ef, const void *ec, hipStream_t s) {
+    const dim3 grid(rows_grid(fine.ny, fine.nz));
+    if (fp32)
+        hipLaunchKernelGGL(mg_prolong_kernel<float>, grid, dim3(256), 0, s,
+                           make_mg_args<float>(fine, coarse, tab, 1.0), (float *)ef,
+                           (const float *)ec);
+    else
+        hipLaunchKernelGGL(mg_prolong_kernel<double>, grid, dim3(256), 0, s,
+                           make_mg_args<double>(fine, coarse, tab, 1.0), (double *)ef,
+                           (const double *)ec);
+    return hipGetLastError();
+}
+
+}  // namespace stk
