@@ -354,13 +354,21 @@ typedef struct {
     double *output_host;
 } smooth_job;
 
-/* Per-job timestamps (steady clock, ns) and accounting. */
+/* Per-job timestamps (steady clock, ns) and accounting.  A job's latency
+ * t_done - t_submit splits into queue (t_admit - t_submit: waiting for pool
+ * space or a slot), upload (t_uploaded - t_admit: host-to-device copy of the
+ * input, including the wait for a copy thread), compute (t_computed -
+ * t_uploaded: the batched iterations that ran its sweeps, including the wait
+ * for the next iteration; t_start marks its first launch) and download
+ * (t_done - t_computed: device-to-host copy of the result). */
 typedef struct {
     int64_t t_submit_ns, t_admit_ns, t_start_ns, t_done_ns;
     uint64_t footprint_bytes;   /* device bytes the job held while resident */
     double lups;                /* lattice-site updates performed (interior sites * sweeps) */
     int32_t batch_id;           /* launch batch that ran the job's sweeps */
     int32_t reserved;
+    int64_t t_uploaded_ns;      /* input resident on the device */
+    int64_t t_computed_ns;      /* last iteration of the job completed */
 } smooth_stats;
 
 /* Create a service: allocates the device pool (hbm_budget_bytes) and starts

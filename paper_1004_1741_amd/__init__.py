@@ -60,7 +60,8 @@ class SmoothStats(ctypes.Structure):
     _fields_ = [("t_submit_ns", ctypes.c_int64), ("t_admit_ns", ctypes.c_int64),
                 ("t_start_ns", ctypes.c_int64), ("t_done_ns", ctypes.c_int64),
                 ("footprint_bytes", ctypes.c_uint64), ("lups", ctypes.c_double),
-                ("batch_id", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("batch_id", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("t_uploaded_ns", ctypes.c_int64), ("t_computed_ns", ctypes.c_int64)]
 
 
 class ServiceStats(ctypes.Structure):

@@ -200,6 +200,7 @@ void uploader(smooth_ctx *c, int k) {
             continue;
         }
         j->ph = PH_READY;
+        j->st.t_uploaded_ns = now_ns();
         c->cv.notify_all();
     }
 }
@@ -416,8 +417,12 @@ void scheduler(smooth_ctx *c) {
         }
         for (Job *j : failed)
             if (j->ph != PH_END) finish(c, j, SMOOTH_FAILED);
+        const int64_t t_iter = now_ns();
         for (Job *j : completed)
-            if (j->ph != PH_END) c->to_download.push_back(j);
+            if (j->ph != PH_END) {
+                j->st.t_computed_ns = t_iter;
+                c->to_download.push_back(j);
+            }
         if (!completed.empty()) c->cv_io.notify_all();
     }
     c->sched_done = true;
