@@ -31,7 +31,37 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-SECTIONS = ("copy", "small", "by_t", "fp32", "gs", "rbgs", "poisson", "serving")
+SECTIONS = ("copy", "small", "by_t", "fp32", "gs", "gs512", "rbgs", "mg", "poisson", "serving")
+
+
+def gs_source_sha():
+    """Hash of the Gauss-Seidel wavefront source (comments and blank lines
+    removed), as recorded in its counter profile."""
+    import hashlib
+    import re
+    src = open(os.path.join(ROOT, "paper_1004_1741_amd", "csrc", "gs.hip")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    lines = [re.sub(r"//.*$", "", ln).rstrip() for ln in src.split("\n")]
+    return hashlib.sha256("\n".join(ln for ln in lines if ln.strip()).encode()).hexdigest()[:16]
+
+
+def measured_gs_traffic(n):
+    """HBM bytes per launch of the wavefront (50 sweeps at n^3) from the
+    committed counter summary, or None if it describes other sources."""
+    prof = os.path.join(ROOT, "profiles", "gs_wavefront_fp64_%dcubed.md" % n)
+    if not os.path.exists(prof):
+        return None
+    vals = {}
+    for line in open(prof):
+        if " = " in line:
+            k, v = line.strip().split(" = ", 1)
+            vals[k] = v
+    if vals.get("kernel_source_sha256_16") != gs_source_sha():
+        return None
+    try:
+        return float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"])
+    except KeyError:
+        return None
 
 
 def bytes_per_lup(elem_bytes: int, t: int) -> float:
@@ -93,15 +123,16 @@ def parse():
     ap.add_argument("--quick", action="store_true", help="headline only (same as --sections none)")
     ap.add_argument("--sections", default="all",
                     help="extra measurements after the headline, comma separated: "
-                         "copy,small,by_t,fp32,gs,rbgs,poisson,serving (or all / none)")
+                         "copy,small,by_t,fp32,gs,gs512,rbgs,mg,poisson,serving (or all / none)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--poisson-n", type=int, default=256)
+    ap.add_argument("--poisson-n", type=int, default=512)
     ap.add_argument("--poisson-m", type=int, default=32, help="inner sweeps per outer round")
-    ap.add_argument("--poisson-methods", default="jacobi,gs,rbgs")
+    ap.add_argument("--poisson-methods", default="rbgs",
+                    help="smoothers of the large Poisson comparison (jacobi,gs,rbgs)")
     ap.add_argument("--poisson-inner", default="fp32_refined,plain_fp64",
                     help="which solves of the Poisson comparison to run")
-    ap.add_argument("--serving-jobs", type=int, default=300)
-    ap.add_argument("--serving-rate", default="200",
+    ap.add_argument("--serving-jobs", type=int, default=2000)
+    ap.add_argument("--serving-rate", default="50,100,200,500",
                     help="arrival rate(s) per second, comma separated")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 2 GiB device copy (counter calibration)")
@@ -209,7 +240,9 @@ def cpu_refine_oracle(ns=(32, 64), m=32, tol=1e-10):
         w = si.poisson(n=n, seed=0)
         fp = w["f"] / float((n + 1) ** 2)
         for method, name in ((0, "jacobi"), (1, "gauss_seidel")):
-            for inner_f32, key in ((True, "fp32_refined"), (False, "plain_fp64")):
+            # the oracle's FP64 variant is the same defect correction with FP64
+            # inner sweeps (the GPU's plain_fp64 smooths u itself)
+            for inner_f32, key in ((True, "fp32_refined"), (False, "fp64_defect_correction")):
                 t0 = time.perf_counter()
                 _, rc, outer, rel = oracle.refine(w["u"], fp, method=method, inner_f32=inner_f32,
                                                   m=m, tol=tol, max_outer=10 ** 6, lib=lib)
@@ -260,8 +293,87 @@ def small_grids(P, torch):
     return out
 
 
+def mg_solves(P, torch, n, keep, seed=0, tol=1e-10):
+    """The Poisson workload solved by multigrid V(2,2)-cycles inside FP64
+    defect correction: every smoother, FP32 and FP64 cycles; time to
+    rel <= tol.  The FP32 red-black solution is kept for the CPU residual
+    check."""
+    import synthetic_inputs as si
+    w = si.poisson(n=n, seed=seed)
+    fp_host = w["f"] / float((n + 1) ** 2)
+    fp = torch.from_numpy(fp_host).to("cuda")
+    out = {}
+    for sm, name in ((2, "red_black"), (1, "gauss_seidel"), (0, "weighted_jacobi")):
+        for fp32, key in ((True, "fp32_cycles"), (False, "fp64_cycles")):
+            u = torch.from_numpy(w["u"]).to("cuda")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            cyc, rel, rc = P.mg_solve(u, fp, smoother=sm, inner_fp32=fp32, pre=2, post=2,
+                                      rel_tol=tol, max_cycles=100, raise_on_noconv=False)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            out["%s_%s" % (name, key)] = {"seconds": round(dt, 4), "cycles": cyc,
+                                          "rel_residual": rel, "status": rc,
+                                          "ms_per_cycle": round(1e3 * dt / max(cyc, 1), 2)}
+            log("mg %d^3 %s %s: %s" % (n, name, key, out["%s_%s" % (name, key)]))
+            if sm == 2 and fp32:
+                keep["mg_%d_red_black_fp32_cycles" % n] = (u.cpu().numpy(), fp_host)
+            del u
+    return out
+
+
+def cpu_residual_check(solutions):
+    """The CPU oracle's own residual ||f' - A u|| / ||f'|| of GPU solutions."""
+    import oracle
+    lib = oracle.load()
+    out = {}
+    for key, (u, fp) in solutions.items():
+        t0 = time.perf_counter()
+        _, rr = oracle.residual(u, fp, lib=lib)
+        rel = float(np.sqrt(rr) / np.sqrt(oracle.sumsq(fp, lib=lib)))
+        out[key] = {"rel_residual": rel, "seconds": round(time.perf_counter() - t0, 2)}
+    return out
+
+
+def cpu_wavefront(n, gs_n=384, sweeps=8):
+    """The paper's own multicore schemes on the host cores (cpu_baseline/):
+    the threaded Jacobi baseline (t = 1) and the temporal wavefront (t = 4, 8)
+    on n^3, the pipeline-parallel Gauss-Seidel (t = 1) and its wavefront
+    (t = 4) on gs_n^3, `sweeps` sweeps each, FP64."""
+    import cpu_baseline as W
+    import synthetic_inputs as si
+    W.build(force=False)
+    threads = min(W.cpu_count(), int(os.environ.get("OMP_NUM_THREADS", "16") or 16), 64)
+    out = {"threads": threads, "host": cpu_model()}
+    u = si.jacobi_512(seed=0, n=n)["u"]
+    scratch = np.empty_like(u)
+    for t in (1, 4, 8):
+        groups = max(1, threads // t)
+        if t > threads:
+            continue
+        by = max(16, n // (2 * groups))  # two y-blocks per group: contiguous rows per plane
+        W.jacobi(u, t, t=t, groups=groups, block_y=by, scratch=scratch)  # first touch
+        t0 = time.perf_counter()
+        W.jacobi(u, sweeps, t=t, groups=groups, block_y=by, scratch=scratch)
+        dt = time.perf_counter() - t0
+        out["jacobi_%d_t%d" % (n, t)] = {"MLUPs": round(float(n) ** 3 * sweeps / dt / 1e6, 1),
+                                         "threads": t * groups, "groups": groups,
+                                         "block_rows": by, "seconds": round(dt, 3)}
+    del u, scratch
+    g = si.gs_384(seed=0, n=gs_n)["u"]
+    for t in (1, 4):
+        P_ = max(1, threads // t)
+        t0 = time.perf_counter()
+        W.gauss_seidel(g, sweeps, t=t, subblocks=P_)
+        dt = time.perf_counter() - t0
+        out["gs_%d_t%d" % (gs_n, t)] = {"MLUPs": round(float(gs_n) ** 3 * sweeps / dt / 1e6, 1),
+                                        "threads": t * P_, "subblocks": P_,
+                                        "seconds": round(dt, 3)}
+    return out
+
+
 def poisson_compare(P, torch, n, seed=0, methods=(0, 1, 2), m=32, tol=1e-10, chunk_s=30.0,
-                    inners=("fp32_refined", "plain_fp64")):
+                    inners=("fp32_refined", "plain_fp64"), keep=None):
     """-Laplace u = f on n^3, h = 1/(n+1), f U[-1,1), u0 = 0: time to reach
     ||f' - A u|| <= tol ||f'|| with the FP32-refined loop and the plain FP64
     method.  The solve runs as consecutive library calls of a bounded number
@@ -303,6 +415,9 @@ def poisson_compare(P, torch, n, seed=0, methods=(0, 1, 2), m=32, tol=1e-10, chu
                         "rel_residual": rel, "status": rc,
                         "MLUPs": round(float(n) ** 3 * sweeps / dt / 1e6)}
             res[key + "_u"] = u
+            if keep is not None:
+                keep["poisson_%d_%s_%s" % (n, name, key)] = (u.cpu().numpy(),
+                                                              fp.cpu().numpy())
             log("poisson %d^3 %s %s: %s" % (n, name, key, {k: v for k, v in res[key].items()}))
         if "fp32_refined_u" in res and "plain_fp64_u" in res:
             a, b = res.pop("fp32_refined_u"), res.pop("plain_fp64_u")
@@ -316,52 +431,100 @@ def poisson_compare(P, torch, n, seed=0, methods=(0, 1, 2), m=32, tol=1e-10, chu
     return out
 
 
-def serving_stream(P, n_jobs, rate, seed=0, budget=32 << 30, max_inflight=64):
-    """Continuous-batching service under a Poisson arrival stream of uneven
-    jobs (extents U{32..256}, Jacobi/GS and FP64/FP32-refined 50/50, 2..20
-    sweeps).  Inputs are generated before the clock starts."""
+def serving_streams(P, n_jobs, rates, seed=0, budget=32 << 30, max_inflight=64, keep=()):
+    """Continuous-batching service under Poisson arrival streams of uneven jobs
+    (extents U{32..256}, Jacobi/GS and FP64/FP32-refined 50/50, 2..20 sweeps;
+    the same jobs at every rate, arrival times scaled by 1/rate).  Inputs are
+    generated once, before any clock starts.  Returns one record per rate and
+    the outputs of the jobs listed in `keep` (from the first rate)."""
     import threading
+    from concurrent.futures import ThreadPoolExecutor
     import synthetic_inputs as si
-    jobs = si.serving_stream(n_jobs=n_jobs, rate_per_s=rate, seed=seed)
-    inputs = [j.make_input() for j in jobs]
-    outputs = [np.empty_like(x) for x in inputs]
-    svc = P.SmoothService(budget, max_inflight=max_inflight)
-    ids = [None] * n_jobs
+    jobs0 = si.serving_stream(n_jobs=n_jobs, rate_per_s=rates[0], seed=seed)
     t0 = time.perf_counter()
+    with ThreadPoolExecutor(max(1, min(16, os.cpu_count() or 1))) as ex:
+        inputs = list(ex.map(lambda jb: jb.make_input(), jobs0))
+    log("serving: %d job inputs generated in %.1f s (%.1f GB)" %
+        (n_jobs, time.perf_counter() - t0, sum(x.nbytes for x in inputs) / 1e9))
+    runs, kept = [], {}
+    for ri, rate in enumerate(rates):
+        jobs = si.serving_stream(n_jobs=n_jobs, rate_per_s=rate, seed=seed)
+        outputs = [None] * n_jobs
+        svc = P.SmoothService(budget, max_inflight=max_inflight)
+        ids = [None] * n_jobs
+        t0 = time.perf_counter()
 
-    def feeder():
-        for k, j in enumerate(jobs):
-            dt = j.arrival_s - (time.perf_counter() - t0)
-            if dt > 0:
-                time.sleep(dt)
-            ids[k] = svc.submit(inputs[k], outputs[k], j.sweeps, method=j.method,
-                                precision=j.precision)
+        def feeder():
+            for k, jb in enumerate(jobs):
+                dt = jb.arrival_s - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+                outputs[k] = np.empty_like(inputs[k])
+                ids[k] = svc.submit(inputs[k], outputs[k], jb.sweeps, method=jb.method,
+                                    precision=jb.precision)
 
-    th = threading.Thread(target=feeder)
-    th.start()
-    th.join()
-    svc.wait_all()
-    wall = time.perf_counter() - t0
-    lat, queue, run, lups = [], [], [], 0.0
-    for k in range(n_jobs):
-        st, stats = svc.poll(ids[k])
-        assert st == P.SmoothService.DONE
-        lat.append((stats.t_done_ns - stats.t_submit_ns) * 1e-6)
-        queue.append((stats.t_admit_ns - stats.t_submit_ns) * 1e-6)
-        run.append((stats.t_done_ns - stats.t_start_ns) * 1e-6)
-        lups += stats.lups
-    info = svc.info()
-    svc.shutdown()
-    lat = np.array(lat)
-    return {"jobs": n_jobs, "rate_per_s": rate, "wall_s": round(wall, 3),
-            "p50_ms": round(float(np.percentile(lat, 50)), 3),
-            "p99_ms": round(float(np.percentile(lat, 99)), 3),
-            "mean_queue_ms": round(float(np.mean(queue)), 3),
-            "mean_start_to_done_ms": round(float(np.mean(run)), 3),
-            "MLUPs_aggregate": round(lups / wall / 1e6),
-            "batches": info.batches, "max_resident": info.max_resident_seen,
-            "footprint_high_water_GB": round(info.footprint_high_water / 1e9, 3),
-            "budget_GB": round(budget / 1e9, 3)}
+        th = threading.Thread(target=feeder)
+        th.start()
+        th.join()
+        svc.wait_all()
+        wall = time.perf_counter() - t0
+        lat, parts, lups = [], {"queue": [], "upload": [], "compute": [], "download": []}, 0.0
+        for k in range(n_jobs):
+            st, stt = svc.poll(ids[k])
+            assert st == P.SmoothService.DONE
+            lat.append((stt.t_done_ns - stt.t_submit_ns) * 1e-6)
+            parts["queue"].append((stt.t_admit_ns - stt.t_submit_ns) * 1e-6)
+            parts["upload"].append((stt.t_uploaded_ns - stt.t_admit_ns) * 1e-6)
+            parts["compute"].append((stt.t_computed_ns - stt.t_uploaded_ns) * 1e-6)
+            parts["download"].append((stt.t_done_ns - stt.t_computed_ns) * 1e-6)
+            lups += stt.lups
+        info = svc.info()
+        svc.shutdown()
+        if ri == 0:
+            kept = {k: outputs[k] for k in keep}
+        del outputs
+        lat = np.array(lat)
+        rec = {"jobs": n_jobs, "rate_per_s": rate, "wall_s": round(wall, 3),
+               "p50_ms": round(float(np.percentile(lat, 50)), 3),
+               "p99_ms": round(float(np.percentile(lat, 99)), 3),
+               "breakdown_ms": {name: {"mean": round(float(np.mean(v)), 3),
+                                       "p50": round(float(np.percentile(v, 50)), 3),
+                                       "p99": round(float(np.percentile(v, 99)), 3)}
+                                for name, v in parts.items()},
+               "MLUPs_aggregate": round(lups / wall / 1e6),
+               "batches": info.batches, "max_resident": info.max_resident_seen,
+               "footprint_high_water_GB": round(info.footprint_high_water / 1e9, 3),
+               "budget_GB": round(budget / 1e9, 3)}
+        runs.append(rec)
+        log("serving: %s" % rec)
+    return runs, jobs0, inputs, kept
+
+
+def cpu_check_serving(jobs, inputs, outputs):
+    """The CPU oracle on a sample of service jobs: FP64 jobs must match it bit
+    for bit, FP32-refined jobs the oracle's emulation of the same steps bit
+    for bit and the FP64 result within 1e-5 of max |u|."""
+    import oracle
+    lib = oracle.load()
+    out = {"jobs": len(outputs), "fp64_bit_exact": 0, "fp32_refined_bit_exact": 0,
+           "fp32_refined_max_rel_err": 0.0}
+    t0 = time.perf_counter()
+    for k, got in outputs.items():
+        jb = jobs[k]
+        u0 = inputs[k]
+        ref64 = oracle.smooth(jb.method, u0, jb.sweeps, lib=lib)
+        if jb.precision == 0:
+            assert np.array_equal(got, ref64), ("service job %d differs from the oracle" % k)
+            out["fp64_bit_exact"] += 1
+        else:
+            emu = oracle.refined_job(jb.method, u0, jb.sweeps, lib=lib)
+            assert np.array_equal(got, emu), ("service job %d differs from the oracle" % k)
+            err = float(np.abs(got - ref64).max() / np.abs(ref64).max())
+            assert err <= 1e-5, (k, err)
+            out["fp32_refined_bit_exact"] += 1
+            out["fp32_refined_max_rel_err"] = max(out["fp32_refined_max_rel_err"], err)
+    out["seconds"] = round(time.perf_counter() - t0, 2)
+    return out
 
 
 def main():
@@ -488,6 +651,29 @@ def main():
             log("gs 384^3 x50 %s: %s" % (key, gs[key]))
         extra["gs_384_x50"] = gs
         del ug, u0
+    if "gs512" in sections:
+        # Gauss-Seidel wavefront at the headline size: 512^3 x 50, all sweeps
+        # in flight (interior 2U-1 seed 0, zero ghosts)
+        g = si.gs_384(seed=0, n=n)
+        ug = torch.from_numpy(g["u"]).to("cuda")
+        u0 = ug.clone()
+        P.gauss_seidel(u0, 50)
+        P.sync()
+        u0.copy_(ug)
+        m = events_time(torch, lambda: P.gauss_seidel(u0, 50), reps=1)
+        P.sync()
+        gbytes = 2 * 8 * float(n) ** 3
+        gl = float(n) ** 3 * 50
+        t1_ms = 50 * gbytes / (HBM_PEAK_GBS * 1e9) * 1e3  # one load + store per site per sweep
+        extra["gs_%d_x50" % n] = {
+            "ms": round(m, 3), "MLUPs": round(gl / (m * 1e-3) / 1e6),
+            "frac_of_t1_roofline": round(t1_ms / m, 4),
+            "hbm_bytes_algorithmic": gbytes,
+            "hbm_frac": round(gbytes / (m * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
+            "traffic": measured_gs_traffic(n),
+            "traffic_unit": "bytes/launch (rocprofv3 FETCH_SIZE+WRITE_SIZE, copy-calibrated)"}
+        log("gs %d^3 x50: %s" % (n, extra["gs_%d_x50" % n]))
+        del ug, u0
     if "rbgs" in sections:
         # red-black Gauss-Seidel on the fused pass, 512^3 x 100 sweeps (FP64)
         rb = {}
@@ -502,24 +688,27 @@ def main():
     # free the 512^3 grids before the remaining measurements
     del u, s
     torch.cuda.empty_cache()
+    solutions = {}  # final GPU iterates whose residual the CPU oracle re-computes
+    if "mg" in sections:
+        extra["mg_poisson_%d" % n] = mg_solves(P, torch, n, solutions)
     if "poisson" in sections and args.poisson_n > 0:
         names = {"jacobi": 0, "gs": 1, "rbgs": 2}
         methods = tuple(names[x] for x in args.poisson_methods.split(","))
         extra["poisson_%d" % args.poisson_n] = poisson_compare(
             P, torch, args.poisson_n, methods=methods, m=args.poisson_m,
-            inners=tuple(args.poisson_inner.split(",")))
+            inners=tuple(args.poisson_inner.split(",")), keep=solutions)
 
     if "poisson" in sections:
         # the sizes the CPU oracle solves too (cpu_oracle_poisson_small)
         for ns in (32, 64):
             extra["poisson_%d" % ns] = poisson_compare(P, torch, ns, m=args.poisson_m)
+    serving_sample = None
     if "serving" in sections and args.serving_jobs > 0:
         rates = [float(x) for x in str(args.serving_rate).split(",")]
-        runs = []
-        for rate in rates:
-            runs.append(serving_stream(P, args.serving_jobs, rate))
-            log("serving: %s" % runs[-1])
+        keep = tuple(range(0, args.serving_jobs, max(1, args.serving_jobs // 16)))[:16]
+        runs, sjobs, sinputs, kept = serving_streams(P, args.serving_jobs, rates, keep=keep)
         extra["serving"] = runs[0] if len(runs) == 1 else runs
+        serving_sample = (sjobs, sinputs, kept)
 
     line = {
         "metric": "MLUP/s & HBM-roofline fraction at 512^3 (FP64 vs FP32-refined); job p50/p99",
@@ -550,6 +739,15 @@ def main():
             log("cpu oracle gs: %s" % extra["cpu_oracle_gs_384_x50"])
         if "poisson" in sections:
             extra["cpu_oracle_poisson_small"] = cpu_refine_oracle()
+        if solutions:
+            extra["cpu_oracle_residual_of_gpu_solutions"] = cpu_residual_check(solutions)
+            log("cpu oracle residuals: %s" % extra["cpu_oracle_residual_of_gpu_solutions"])
+        if serving_sample is not None:
+            sjobs, sinputs, kept = serving_sample
+            extra["cpu_oracle_serving_sample"] = cpu_check_serving(sjobs, sinputs, kept)
+            log("cpu oracle serving sample: %s" % extra["cpu_oracle_serving_sample"])
+        extra["cpu_wavefront"] = cpu_wavefront(n)
+        log("cpu wavefront: %s" % extra["cpu_wavefront"])
     line.update(extra)
     print(json.dumps(line), flush=True)
 

@@ -22,7 +22,7 @@ import numpy as np
 _HERE = pathlib.Path(__file__).resolve().parent
 _SRC = _HERE / "wavefront.c"
 _LIB_PATH = _HERE / "libwavefront.so"
-CFLAGS = ["-O3", "-ffp-contract=off", "-fno-fast-math", "-fno-unsafe-math-optimizations",
+CFLAGS = ["-O3", "-march=x86-64-v3", "-ffp-contract=off", "-fno-fast-math", "-fno-unsafe-math-optimizations",
           "-pthread", "-fPIC", "-shared", "-std=c11"]
 
 _lib = None

@@ -35,7 +35,8 @@
  * array of (nz+2h)(ny+2h)(nx+2h) doubles, x contiguous; f (optional) is
  * interior-only, nz*ny*nx values.
  *
- * Build: gcc -O3 -ffp-contract=off -fno-fast-math -pthread -shared -fPIC
+ * Build: gcc -O3 -march=x86-64-v3 -ffp-contract=off -fno-fast-math -pthread -shared -fPIC
+ * (AVX2 vectors; contraction off, so every element sees the same operations)
  */
 #define _GNU_SOURCE
 #include <pthread.h>
