@@ -558,7 +558,9 @@ int stencil_mg_solve(const st_grid *grid, int32_t smoother, int32_t inner_dtype,
     }
     std::vector<unsigned char> tb;
     std::vector<MgTables> tabs(nlev > 1 ? nlev - 1 : 0);
-    for (int l = 0; l + 1 < nlev; ++l) mg_build_tables(f32, lv[l], tb, tabs[l]);
+    for (int l = 0; l + 1 < nlev; ++l)
+        if (!mg_build_tables(f32, lv[l], tb, tabs[l]))
+            return fail(ST_EINVAL, "multigrid transfer support too wide for this grid");
     const size_t tab_off = total;
     total += up(tb.size());
     const int nb = residual_partial_count(g);

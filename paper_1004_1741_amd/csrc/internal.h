@@ -155,7 +155,7 @@ struct MgTables {
     void *dev = nullptr;
     size_t off_i0[3], off_wm[3], off_wq[3], off_lo[3], off_hi[3];
 };
-void mg_build_tables(bool fp32, const Geom &fine, std::vector<unsigned char> &bytes,
+bool mg_build_tables(bool fp32, const Geom &fine, std::vector<unsigned char> &bytes,
                      MgTables &tab);
 // res = r - ((6*c) - s) (e padded; r, res interior-only).
 hipError_t launch_mg_residual(bool fp32, const Geom &g, const void *e, const void *r, void *res,

@@ -35,6 +35,10 @@
 namespace stk {
 namespace {
 
+// Largest number of fine points with a non-zero weight towards one coarse
+// point, per axis (nc + 1 = floor((n+1)/2) gives at most 4; the host checks).
+constexpr int MG_MAXS = 5;
+
 template <typename T>
 struct MgAxisDev {
     const int *i0;   // [n + 1]: coarse index I0 of fine point i (entry 0 unused)
@@ -86,7 +90,10 @@ __device__ __forceinline__ T axis_w(const MgAxisDev<T> &a, int i, int I) {
     return I == i0 ? a.wm[i] : (I == i0 + 1 ? a.wq[i] : T(0));
 }
 
-// r_c = scale * P^T res (both interior-only); one wave per coarse row.
+// r_c = scale * P^T res (both interior-only); one wave per coarse row.  The
+// weights of a coarse point's fine support (at most MG_MAXS points per axis)
+// are read once into registers: the y and z ones are the same for the whole
+// wave, the x ones per lane.
 template <typename T>
 __global__ void __launch_bounds__(256) mg_restrict_kernel(MgArgs<T> M,
                                                           const T *__restrict__ res,
@@ -97,19 +104,37 @@ __global__ void __launch_bounds__(256) mg_restrict_kernel(MgArgs<T> M,
     const int J = (blockIdx.x - (K - 1) * rows_per_plane) * 4 + w + 1;
     if (J > M.cny) return;
     const MgAxisDev<T> &ax = M.ax[0], &ay = M.ax[1], &az = M.ax[2];
-    const int j0 = ay.lo[J], j1 = ay.hi[J], k0 = az.lo[K], k1 = az.hi[K];
+    const int j0 = ay.lo[J], nj = ay.hi[J] - j0 + 1, k0 = az.lo[K], nk = az.hi[K] - k0 + 1;
+    T wy[MG_MAXS], wz[MG_MAXS];
+#pragma unroll
+    for (int q = 0; q < MG_MAXS; ++q) {
+        wy[q] = q < nj ? axis_w(ay, j0 + q, J) : T(0);
+        wz[q] = q < nk ? axis_w(az, k0 + q, K) : T(0);
+    }
     for (int I = lane + 1; I <= M.cnx; I += 64) {
-        const int i0 = ax.lo[I], i1 = ax.hi[I];
+        const int i0 = ax.lo[I], ni = ax.hi[I] - i0 + 1;
+        T wx[MG_MAXS];
+#pragma unroll
+        for (int q = 0; q < MG_MAXS; ++q) wx[q] = q < ni ? axis_w(ax, i0 + q, I) : T(0);
         T zs = T(0);
-        for (int k = k0; k <= k1; ++k) {
+#pragma unroll
+        for (int c = 0; c < MG_MAXS; ++c) {
+            if (c >= nk) break;
             T ys = T(0);
-            for (int j = j0; j <= j1; ++j) {
-                const T *row = res + ((int64_t)(k - 1) * M.fny + (j - 1)) * M.fnx;
+#pragma unroll
+            for (int b = 0; b < MG_MAXS; ++b) {
+                if (b >= nj) break;
+                const T *row = res + ((int64_t)(k0 + c - 1) * M.fny + (j0 + b - 1)) * M.fnx +
+                               (i0 - 1);
                 T xs = T(0);
-                for (int i = i0; i <= i1; ++i) xs = xs + (axis_w(ax, i, I) * row[i - 1]);
-                ys = ys + (axis_w(ay, j, J) * xs);
+#pragma unroll
+                for (int a = 0; a < MG_MAXS; ++a) {
+                    if (a >= ni) break;
+                    xs = xs + (wx[a] * row[a]);
+                }
+                ys = ys + (wy[b] * xs);
             }
-            zs = zs + (axis_w(az, k, K) * ys);
+            zs = zs + (wz[c] * ys);
         }
         rc[((int64_t)(K - 1) * M.cny + (J - 1)) * M.cnx + (I - 1)] = zs * M.scale;
     }
@@ -168,9 +193,11 @@ MgArgs<T> make_mg_args(const Geom &fine, const Geom &coarse, const MgTables &tab
     return M;
 }
 
-// Host tables of one axis in precision T, appended to `bytes`.
+// Host tables of one axis in precision T, appended to `bytes`.  False if a
+// coarse point's support exceeds MG_MAXS fine points (never for
+// nc + 1 = floor((n+1)/2), where it is at most 4).
 template <typename T>
-void axis_tables(int n, int nc, std::vector<unsigned char> &bytes, size_t off[5]) {
+bool axis_tables(int n, int nc, std::vector<unsigned char> &bytes, size_t off[5]) {
     auto put = [&](const void *p, size_t nbytes) {
         const size_t o = (bytes.size() + 255) / 256 * 256;
         bytes.resize(o + nbytes);
@@ -191,12 +218,14 @@ void axis_tables(int n, int nc, std::vector<unsigned char> &bytes, size_t off[5]
         int64_t h = ((int64_t)(I + 1) * (n + 1) - 1) / (nc + 1);
         lo[I] = (int)(l < 1 ? 1 : l);
         hi[I] = (int)(h > n ? n : h);
+        if (hi[I] - lo[I] + 1 > MG_MAXS) return false;
     }
     off[0] = put(i0.data(), i0.size() * sizeof(int));
     off[1] = put(wm.data(), wm.size() * sizeof(T));
     off[2] = put(wq.data(), wq.size() * sizeof(T));
     off[3] = put(lo.data(), lo.size() * sizeof(int));
     off[4] = put(hi.data(), hi.size() * sizeof(int));
+    return true;
 }
 
 }  // namespace
@@ -211,21 +240,21 @@ double mg_scale(const Geom &g) {
     return std::cbrt(rx * ry * rz);
 }
 
-void mg_build_tables(bool fp32, const Geom &fine, std::vector<unsigned char> &bytes,
+bool mg_build_tables(bool fp32, const Geom &fine, std::vector<unsigned char> &bytes,
                      MgTables &tab) {
     const int n[3] = {fine.nx, fine.ny, fine.nz};
     for (int d = 0; d < 3; ++d) {
         size_t off[5];
-        if (fp32)
-            axis_tables<float>(n[d], mg_coarse_n(n[d]), bytes, off);
-        else
-            axis_tables<double>(n[d], mg_coarse_n(n[d]), bytes, off);
+        const bool ok = fp32 ? axis_tables<float>(n[d], mg_coarse_n(n[d]), bytes, off)
+                             : axis_tables<double>(n[d], mg_coarse_n(n[d]), bytes, off);
+        if (!ok) return false;
         tab.off_i0[d] = off[0];
         tab.off_wm[d] = off[1];
         tab.off_wq[d] = off[2];
         tab.off_lo[d] = off[3];
         tab.off_hi[d] = off[4];
     }
+    return true;
 }
 
 static unsigned rows_grid(int ny, int nz) { return (unsigned)((int64_t)nz * ((ny + 3) / 4)); }
