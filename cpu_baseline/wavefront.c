@@ -91,6 +91,42 @@ static void barrier_wait(spin_barrier *b, int *local_sense)
     }
 }
 
+/* Start gate of a team of threads: every worker waits on it before doing
+ * anything, and the launcher opens it (1) once all threads exist.  If a
+ * thread cannot be created, the gate is set to abort (-1) instead and the
+ * workers already started return at once, so none of them waits in a
+ * barrier that could never fill. */
+static int wait_gate(_Atomic int *gate)
+{
+    int g, spins = 0;
+    while ((g = atomic_load_explicit(gate, memory_order_acquire)) == 0) {
+        if (++spins < 2048) {
+            CPU_RELAX();
+        } else {
+            sched_yield();
+            spins = 0;
+        }
+    }
+    return g > 0;
+}
+
+static int run_threads(int n, void *(*fn)(void *), void *args, size_t argsz, _Atomic int *gate)
+{
+    pthread_t *tid = (pthread_t *)malloc((size_t)n * sizeof(pthread_t));
+    if (!tid) return -2;
+    atomic_store(gate, 0);
+    int started = 0, rc = 0;
+    for (; started < n; started++)
+        if (pthread_create(&tid[started], NULL, fn, (char *)args + (size_t)started * argsz)) {
+            rc = -3;
+            break;
+        }
+    atomic_store_explicit(gate, rc == 0 ? 1 : -1, memory_order_release);
+    for (int i = 0; i < started; i++) pthread_join(tid[i], NULL);
+    free(tid);
+    return rc;
+}
+
 /* --------------------------------------------------------- row update ---- */
 
 /* One row of sites i = h .. h+nx-1 of a Jacobi level: c is the row of the
@@ -191,6 +227,7 @@ typedef struct {
     double **bnd;          /* [slot][level 1..t-1] nz * 2 rows of px */
     int nslots;
     spin_barrier bar;
+    _Atomic int gate;
 } jac_ctx;
 
 typedef struct {
@@ -239,6 +276,7 @@ static void *jac_worker(void *arg)
     const int64_t nsteps = c->nz + 2 * (c->t - 1);
     const int rounds = (c->nblocks + c->groups - 1) / c->groups;
     int sense = 0;
+    if (!wait_gate(&c->gate)) return NULL;
     for (int rd = 0; rd < rounds; rd++) {
         const int b = rd * c->groups + grp;
         const int active = b < c->nblocks && tau <= c->levels;
@@ -278,22 +316,6 @@ static void *jac_worker(void *arg)
     return NULL;
 }
 
-static int run_threads(int n, void *(*fn)(void *), void *args, size_t argsz)
-{
-    pthread_t *tid = (pthread_t *)malloc((size_t)n * sizeof(pthread_t));
-    if (!tid) return -2;
-    int started = 0, rc = 0;
-    for (; started < n; started++)
-        if (pthread_create(&tid[started], NULL, fn, (char *)args + (size_t)started * argsz)) {
-            rc = -3;
-            break;
-        }
-    /* a thread that failed to start would leave the others in the barrier:
-     * only reachable before any barrier when started == 0 */
-    for (int i = 0; i < started; i++) pthread_join(tid[i], NULL);
-    free(tid);
-    return rc;
-}
 
 /* Plan of the y-blocks: nblocks blocks of about block_y rows; every block but
  * the last needs at least t + 2 rows so that the two kept rows of each level
@@ -368,7 +390,7 @@ int wf_jacobi_f64(int64_t nx, int64_t ny, int64_t nz, int64_t h, double *u, doub
                 th[gi * t + ti].grp = gi;
                 th[gi * t + ti].tau = ti + 1;
             }
-        rc = run_threads(groups * t, jac_worker, th, sizeof(jac_thread));
+        rc = run_threads(groups * t, jac_worker, th, sizeof(jac_thread), &c.gate);
         done += c.levels;
         double *tmp = A;
         A = B;
@@ -393,6 +415,7 @@ typedef struct {
     int t, P, levels;
     const int64_t *jb; /* sub-block row starts jb[0..P] */
     spin_barrier bar;
+    _Atomic int gate;
 } gs_ctx;
 
 typedef struct {
@@ -408,6 +431,7 @@ static void *gs_worker(void *arg)
     const int64_t nsteps = c->nz + (c->P - 1) + 2 * (c->t - 1);
     const int active = th->tau < c->levels;
     int sense = 0;
+    if (!wait_gate(&c->gate)) return NULL;
     for (int64_t s = 0; s < nsteps; s++) {
         const int64_t k = h + s - th->p - 2 * th->tau;
         if (active && k >= h && k < h + c->nz) {
@@ -456,7 +480,7 @@ int wf_gs_f64(int64_t nx, int64_t ny, int64_t nz, int64_t h, double *u, const do
                 th[ti * P + p].tau = ti;
                 th[ti * P + p].p = p;
             }
-        rc = run_threads(t * P, gs_worker, th, sizeof(gs_thread));
+        rc = run_threads(t * P, gs_worker, th, sizeof(gs_thread), &c.gate);
         done += c.levels;
     }
     free(th);
