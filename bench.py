@@ -431,7 +431,8 @@ def poisson_compare(P, torch, n, seed=0, methods=(0, 1, 2), m=32, tol=1e-10, chu
     return out
 
 
-def serving_streams(P, n_jobs, rates, seed=0, budget=32 << 30, max_inflight=64, keep=()):
+def serving_streams(P, n_jobs, rates, seed=0, budget=32 << 30, max_inflight=64, keep=(),
+                    sweeps_per_iteration=0):
     """Continuous-batching service under Poisson arrival streams of uneven jobs
     (extents U{32..256}, Jacobi/GS and FP64/FP32-refined 50/50, 2..20 sweeps;
     the same jobs at every rate, arrival times scaled by 1/rate).  Inputs are
@@ -468,7 +469,8 @@ def serving_streams(P, n_jobs, rates, seed=0, budget=32 << 30, max_inflight=64, 
         outputs = [None] * n_jobs
         owner = [None] * npool
         waits = [0]
-        svc = P.SmoothService(budget, max_inflight=max_inflight)
+        svc = P.SmoothService(budget, max_inflight=max_inflight,
+                              sweeps_per_iteration=sweeps_per_iteration)
         ids = [None] * n_jobs
         t0 = time.perf_counter()
 

@@ -321,7 +321,10 @@ typedef struct {
     int32_t max_inflight;       /* resident jobs at most (>= 1) */
     int32_t device;             /* HIP device ordinal */
     int32_t t_fuse;             /* fused sweeps per Jacobi pass (0 = automatic, 1..8, 16) */
-    int32_t reserved;
+    int32_t sweeps_per_iteration; /* sweeps a resident job may do per batched iteration before
+                                     the scheduler admits new jobs and finishes others: 0 = all
+                                     of its sweeps (default); else at most this many (whole
+                                     Jacobi passes, at least one).  Results do not depend on it. */
 } smooth_config;
 
 enum { SMOOTH_JACOBI = 0, SMOOTH_GS = 1 };

@@ -45,7 +45,7 @@ class Weights(ctypes.Structure):
 class SmoothConfig(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_inflight", ctypes.c_int32),
                 ("device", ctypes.c_int32), ("t_fuse", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("sweeps_per_iteration", ctypes.c_int32)]
 
 
 class SmoothJob(ctypes.Structure):
@@ -347,8 +347,10 @@ class SmoothService:
 
     QUEUED, RUNNING, DONE, FAILED, CANCELED = 0, 1, 2, 3, 4
 
-    def __init__(self, hbm_budget_bytes, max_inflight=64, device=0, t_fuse=0):
-        cfg = SmoothConfig(int(hbm_budget_bytes), int(max_inflight), int(device), int(t_fuse), 0)
+    def __init__(self, hbm_budget_bytes, max_inflight=64, device=0, t_fuse=0,
+                 sweeps_per_iteration=0):
+        cfg = SmoothConfig(int(hbm_budget_bytes), int(max_inflight), int(device), int(t_fuse),
+                           int(sweeps_per_iteration))
         self._ctx = ctypes.c_void_p(None)
         _check(lib().smooth_init(ctypes.byref(cfg), ctypes.byref(self._ctx)))
         self._keep = {}

@@ -4,12 +4,13 @@
 //   * scheduler: admits queued jobs while their device footprint fits the
 //     pool (one hipMalloc of hbm_budget_bytes, first-fit sub-allocation) and
 //     fewer than max_inflight are resident, then runs *iterations*: every
-//     resident job whose input is on the device advances by one pass, and all
-//     jobs of the same kind share one batched launch (one Jacobi pass kernel
-//     per dtype/t group, one merged-ticket Gauss-Seidel wavefront per group).
-//     Jobs admitted while an iteration runs join the next one, so their work
-//     overlaps with the others' on the device (iteration-level continuous
-//     batching);
+//     resident job whose input is on the device does its sweeps (all of them,
+//     or at most sweeps_per_iteration) in rounds of batched launches, where
+//     all jobs of the same kind share one launch (one Jacobi pass kernel per
+//     dtype/t group and round, one merged-ticket Gauss-Seidel wavefront per
+//     group).  Jobs admitted while an iteration runs join the next one, so
+//     their work overlaps with the others' on the device (iteration-level
+//     continuous batching);
 //   * uploaders / downloaders (kIoThreads of each): host<->device copies of
 //     job grids on their own streams, so copies overlap with the iterations
 //     and with each other (a single copy thread is limited by the runtime's
@@ -109,7 +110,6 @@ struct smooth_ctx {
     std::vector<std::thread> th_up, th_down;
     int64_t batches = 0, n_done = 0, n_failed = 0, n_canceled = 0;
     int max_resident = 0;
-    int gs_chunk = 4;  // Gauss-Seidel sweeps per iteration
     std::map<int, std::pair<void *, size_t>> jac_tables;   // group -> device table
     std::map<int, std::unique_ptr<GsBatchWork>> gs_works;  // group -> workspace
 };
@@ -247,8 +247,6 @@ hipError_t run_iteration(smooth_ctx *c, const std::vector<Job *> &act, int64_t b
                          std::vector<Job *> *completed, std::vector<Job *> *failed,
                          std::vector<Job *> *gs_ran) {
     hipStream_t s = c->s_comp;
-    std::map<int, JacGroup> jg;
-    std::map<int, GsGroup> gg;
     for (Job *j : act) {
         const double a = j->spec.weights.center, b = j->spec.weights.neighbor;
         const bool ha = a != 0.0;
@@ -270,93 +268,114 @@ hipError_t run_iteration(smooth_ctx *c, const std::vector<Job *> &act, int64_t b
             }
             j->ph = j->spec.sweeps > 0 ? PH_PASSES : PH_FINISH;
         }
-        if (j->ph == PH_PASSES) {
-            const bool f32 = j->refined;
-            if (!j->gs) {
-                const int tb = j->plan[j->pass];
-                const int key = (f32 ? 1000 : 0) + tb * 10 + (ha ? 2 : 0) + (f32 ? 1 : 0);
-                JacGroup &G = jg[key];
-                G.fp32 = f32;
-                G.tb = tb;
-                G.ha = ha;
-                G.hf = f32;
-                JacBatchItem it;
-                it.g = j->g;
-                if (!f32) {
-                    it.src = j->parity ? (const void *)j->s64 : (const void *)j->u;
-                    it.dst = j->parity ? (void *)j->u : (void *)j->s64;
-                    it.f = nullptr;
-                    it.gw = 0.0;
+    }
+    // Rounds of batched launches: every job still in its passes takes one
+    // more Jacobi pass or its next block of Gauss-Seidel sweeps per round,
+    // until it has done sweeps_per_iteration sweeps in this iteration (0 =
+    // all of them); a job's launches follow each other on the stream.
+    std::map<Job *, int> done_now;
+    const int spi = c->cfg.sweeps_per_iteration;
+    for (;;) {
+        std::map<int, JacGroup> jg;
+        std::map<int, GsGroup> gg;
+        for (Job *j : act) {
+            if (j->ph != PH_PASSES) continue;
+            if (std::find(failed->begin(), failed->end(), j) != failed->end()) continue;
+            if (spi > 0 && done_now[j] >= spi) continue;
+            const double a = j->spec.weights.center, b = j->spec.weights.neighbor;
+            const bool ha = a != 0.0;
+            {
+                const bool f32 = j->refined;
+                if (!j->gs) {
+                    const int tb = j->plan[j->pass];
+                    const int key = (f32 ? 1000 : 0) + tb * 10 + (ha ? 2 : 0) + (f32 ? 1 : 0);
+                    JacGroup &G = jg[key];
+                    G.fp32 = f32;
+                    G.tb = tb;
+                    G.ha = ha;
+                    G.hf = f32;
+                    JacBatchItem it;
+                    it.g = j->g;
+                    if (!f32) {
+                        it.src = j->parity ? (const void *)j->s64 : (const void *)j->u;
+                        it.dst = j->parity ? (void *)j->u : (void *)j->s64;
+                        it.f = nullptr;
+                        it.gw = 0.0;
+                    } else {
+                        it.src = j->parity ? (const void *)j->s32 : (const void *)j->e32;
+                        it.dst = j->parity ? (void *)j->e32 : (void *)j->s32;
+                        it.f = j->r32;
+                        it.gw = 1.0;
+                    }
+                    it.a = a;
+                    it.b = b;
+                    G.items.push_back(it);
+                    G.jobs.push_back(j);
                 } else {
-                    it.src = j->parity ? (const void *)j->s32 : (const void *)j->e32;
-                    it.dst = j->parity ? (void *)j->e32 : (void *)j->s32;
-                    it.f = j->r32;
-                    it.gw = 1.0;
+                    const int key = 100000 + (f32 ? 10 : 0) + (ha ? 2 : 0) + (f32 ? 1 : 0);
+                    GsGroup &G = gg[key];
+                    G.fp32 = f32;
+                    G.ha = ha;
+                    G.hf = f32;
+                    GsBatchItem it;
+                    it.g = j->g;
+                    it.u = f32 ? (void *)j->e32 : (void *)j->u;
+                    it.f = f32 ? (const void *)j->r32 : nullptr;
+                    it.a = a;
+                    it.b = b;
+                    it.gw = f32 ? 1.0 : 0.0;
+                    const int left = j->spec.sweeps - j->sweeps_done;
+                    it.sweeps = spi > 0 ? std::min(spi - done_now[j], left) : left;
+                    G.items.push_back(it);
+                    G.jobs.push_back(j);
+                    G.n.push_back(it.sweeps);
                 }
-                it.a = a;
-                it.b = b;
-                G.items.push_back(it);
-                G.jobs.push_back(j);
-            } else {
-                const int key = 100000 + (f32 ? 10 : 0) + (ha ? 2 : 0) + (f32 ? 1 : 0);
-                GsGroup &G = gg[key];
-                G.fp32 = f32;
-                G.ha = ha;
-                G.hf = f32;
-                GsBatchItem it;
-                it.g = j->g;
-                it.u = f32 ? (void *)j->e32 : (void *)j->u;
-                it.f = f32 ? (const void *)j->r32 : nullptr;
-                it.a = a;
-                it.b = b;
-                it.gw = f32 ? 1.0 : 0.0;
-                it.sweeps = std::min(c->gs_chunk, j->spec.sweeps - j->sweeps_done);
-                G.items.push_back(it);
-                G.jobs.push_back(j);
-                G.n.push_back(it.sweeps);
             }
         }
-    }
-    // batched launches
-    for (auto &kv : jg) {
-        JacGroup &G = kv.second;
-        hipError_t e = hipSuccess;
-        auto &tab = c->jac_tables[kv.first];
-        const size_t need = jacobi_batch_table_bytes((int)G.items.size());
-        if (tab.second < need) {
-            if (tab.first) (void)hipFree(tab.first);
-            tab.first = nullptr;
-            tab.second = 0;
-            e = hipMalloc(&tab.first, need * 2);
-            if (e == hipSuccess) tab.second = need * 2;
+        if (jg.empty() && gg.empty()) break;
+        // batched launches of this round
+        for (auto &kv : jg) {
+            JacGroup &G = kv.second;
+            hipError_t e = hipSuccess;
+            auto &tab = c->jac_tables[kv.first];
+            const size_t need = jacobi_batch_table_bytes((int)G.items.size());
+            if (tab.second < need) {
+                if (tab.first) (void)hipFree(tab.first);
+                tab.first = nullptr;
+                tab.second = 0;
+                e = hipMalloc(&tab.first, need * 2);
+                if (e == hipSuccess) tab.second = need * 2;
+            }
+            if (e == hipSuccess)
+                e = launch_jacobi_batch(G.fp32, G.tb, G.ha, G.hf, G.items, tab.first, G.staging, s);
+            if (e != hipSuccess) {
+                for (Job *j : G.jobs) failed->push_back(j);
+                continue;
+            }
+            for (Job *j : G.jobs) {
+                done_now[j] += G.tb;
+                j->parity ^= 1;
+                if (++j->pass == j->plan.size()) j->ph = PH_FINISH;
+            }
         }
-        if (e == hipSuccess)
-            e = launch_jacobi_batch(G.fp32, G.tb, G.ha, G.hf, G.items, tab.first, G.staging, s);
-        if (e != hipSuccess) {
-            for (Job *j : G.jobs) failed->push_back(j);
-            continue;
+        for (auto &kv : gg) {
+            GsGroup &G = kv.second;
+            auto &w = c->gs_works[kv.first];
+            if (!w) w.reset(new GsBatchWork());
+            const hipError_t e = launch_gs_batch(G.fp32, G.ha, G.hf, G.items, *w, s);
+            if (e != hipSuccess) {
+                for (Job *j : G.jobs) failed->push_back(j);
+                continue;
+            }
+            for (size_t i = 0; i < G.jobs.size(); ++i) {
+                Job *j = G.jobs[i];
+                if (std::find(gs_ran->begin(), gs_ran->end(), j) == gs_ran->end()) gs_ran->push_back(j);
+                done_now[j] += G.n[i];
+                j->sweeps_done += G.n[i];
+                if (j->sweeps_done >= j->spec.sweeps) j->ph = PH_FINISH;
+            }
         }
-        for (Job *j : G.jobs) {
-            j->parity ^= 1;
-            if (++j->pass == j->plan.size()) j->ph = PH_FINISH;
-        }
-    }
-    for (auto &kv : gg) {
-        GsGroup &G = kv.second;
-        auto &w = c->gs_works[kv.first];
-        if (!w) w.reset(new GsBatchWork());
-        const hipError_t e = launch_gs_batch(G.fp32, G.ha, G.hf, G.items, *w, s);
-        if (e != hipSuccess) {
-            for (Job *j : G.jobs) failed->push_back(j);
-            continue;
-        }
-        for (size_t i = 0; i < G.jobs.size(); ++i) {
-            Job *j = G.jobs[i];
-            gs_ran->push_back(j);
-            j->sweeps_done += G.n[i];
-            if (j->sweeps_done >= j->spec.sweeps) j->ph = PH_FINISH;
-        }
-    }
+    }  // rounds
     // jobs whose sweeps are done: FP64 correction for refined jobs, then hand
     // over to the downloader
     for (Job *j : act) {
@@ -450,6 +469,8 @@ extern "C" {
 int smooth_init(const smooth_config *cfg, smooth_ctx **out) {
     if (!cfg || !out) return fail(ST_EINVAL, "config and out must not be NULL");
     if (cfg->max_inflight < 1) return fail(ST_EINVAL, "max_inflight must be >= 1");
+    if (cfg->sweeps_per_iteration < 0)
+        return fail(ST_EINVAL, "sweeps_per_iteration must be >= 0");
     if (cfg->hbm_budget_bytes < 4096) return fail(ST_EINVAL, "hbm_budget_bytes too small");
     if (!((cfg->t_fuse >= 0 && cfg->t_fuse <= 8) || cfg->t_fuse == 16))
         return fail(ST_EINVAL, "t_fuse must be 0..8 or 16");

@@ -152,6 +152,8 @@ def test_service_validation(P):
                          ctypes.byref(ctx)) == P.ST.EINVAL
     assert L.smooth_init(ctypes.byref(P.SmoothConfig(1 << 20, 4, 0, 9, 0)),
                          ctypes.byref(ctx)) == P.ST.EINVAL
+    assert L.smooth_init(ctypes.byref(P.SmoothConfig(1 << 20, 4, 0, 0, -1)),
+                         ctypes.byref(ctx)) == P.ST.EINVAL
     assert L.smooth_init(None, ctypes.byref(ctx)) == P.ST.EINVAL
     jid = ctypes.c_uint64(0)
     st = ctypes.c_int32(0)
