@@ -159,9 +159,10 @@ def _expected(j, olib):
     return oracle.refined_job(j["method"], j["u"], j["sweeps"], a=j["a"], b=j["b"], lib=olib)
 
 
-def _serve(P, jobs, budget, max_inflight):
+def _serve(P, jobs, budget, max_inflight, sweeps_per_iteration=0):
     outs = [np.zeros_like(j["u"]) for j in jobs]
-    with P.SmoothService(budget, max_inflight=max_inflight) as svc:
+    with P.SmoothService(budget, max_inflight=max_inflight,
+                         sweeps_per_iteration=sweeps_per_iteration) as svc:
         ids = [svc.submit(j["u"], o, j["sweeps"], method=j["method"], precision=j["prec"],
                           a=j["a"], b=j["b"]) for j, o in zip(jobs, outs)]
         svc.wait_all(timeout_ms=120000)
@@ -191,12 +192,19 @@ def test_service_mixed_stream(P, olib):
     assert info.batches >= 1
 
 
-def test_service_alone_equals_mixed(P, olib):
+@pytest.mark.parametrize("spi", [0, 3])
+def test_service_alone_equals_mixed(P, olib, spi):
+    """Each job gives the same result alone and in a mix, whether it runs all
+    its sweeps in one iteration (0) or at most 3 per iteration; the mix also
+    equals the oracle."""
     jobs = _jobs(seed=2, n=10)
-    mixed, _, info = _serve(P, jobs, 64 << 20, max_inflight=10)
+    say("service alone vs mixed, sweeps_per_iteration=%d" % spi)
+    mixed, states, info = _serve(P, jobs, 64 << 20, max_inflight=10, sweeps_per_iteration=spi)
     assert info.max_resident_seen >= 2  # jobs really shared iterations
     for k, j in enumerate(jobs):
-        alone, st, _ = _serve(P, [j], 64 << 20, max_inflight=1)
+        assert states[k][0] == P.SmoothService.DONE, k
+        assert_same(mixed[k], _expected(j, olib), "job %d mixed vs oracle" % k)
+        alone, st, _ = _serve(P, [j], 64 << 20, max_inflight=1, sweeps_per_iteration=spi)
         assert st[0][0] == P.SmoothService.DONE
         assert_same(alone[0], mixed[k], "job %d alone vs mixed" % k)
 
