@@ -63,8 +63,10 @@ int check_grid(const st_grid *g, Geom *out) {
 bool valid_t(int t) { return (t >= 0 && t <= 8) || t == 16; }
 
 // Automatic depth, measured at 512^3 on MI355X (100 sweeps; 32 with f):
-// FP64 t=5 (12.8 ms vs 14.0 at t=4), with f t=4 (the f ring fits LDS);
-// FP32 t=5, with f t=6.
+// FP64 t=5 (588 us per pass, 118 us per sweep; t=4 493 us, 123 per sweep;
+// t=6 ties per sweep but 100 is not a multiple of 6), with f t=4 (32 sweeps
+// in 8 passes; t=5 needs 8 passes too, two of them of one sweep); FP32 t=5,
+// with f t=6.
 int auto_t(int dtype, bool rhs) {
     if (dtype == ST_FP32) return rhs ? 6 : 5;
     return rhs ? 4 : 5;
@@ -120,12 +122,15 @@ int run_jacobi(const Geom &g, bool fp32, void *u, void *scratch, const void *f, 
     return ST_OK;
 }
 
-// Red-black sweeps per pass: at most 4 (8 levels on chip).  Automatic: FP64
-// 2 (4 levels; 512^3 x 100 on MI355X: t=1 50.6 ms, 2: 29.2, 3: 30.5, 4: 41.0;
-// with a right-hand side only 4 levels keep the f ring in LDS), FP32 3.
+// Red-black sweeps per pass: at most 4 (8 levels on chip).  Automatic: 2
+// (4 levels).  512^3 on MI355X, us per pass at 1/2/3/4 sweeps per pass: FP64
+// 502/514/758/1235, FP32 345/305/453/689.  Three per pass ties two per sweep
+// but splits 32-sweep rounds unevenly (10 passes of 3 and two of 1); with a
+// right-hand side only 4 levels keep the f ring in LDS.
 int rb_sweeps_per_pass(int t_fuse, bool fp32, bool rhs) {
     (void)rhs;
-    int t = t_fuse == 0 ? (fp32 ? 3 : 2) : t_fuse;
+    (void)fp32;
+    int t = t_fuse == 0 ? 2 : t_fuse;
     return t > 4 ? 4 : t;
 }
 

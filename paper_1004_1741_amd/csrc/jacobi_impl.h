@@ -153,13 +153,23 @@ __device__ __forceinline__ void jacobi_tile(const JacArgs<T> &A, int tx, int ty,
     // used; otherwise every level loads its own f plane
     constexpr bool FPRE = RING;
     const int lane = threadIdx.x & 63;
-    const int w = threadIdx.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int h = A.h;
     // Row stores as unconditional buffer stores (see the store at the end of
     // a step) where one point per lane is stored.  The FP64 depth-4 tile with
     // a right-hand side already sits at the register limit, and the store
     // offsets make it spill (measured slower), so it keeps plain stores.
     constexpr bool BUF_STORE = VX == 1 && !(sizeof(T) == 8 && TB == 4 && HAS_F);
+    // Row-major steady-state steps (step_rows) where they measured faster on
+    // MI355X at 512^3: tiles of one site per lane (two per lane were slower),
+    // three or more levels, with a right-hand side only from five levels up
+    // and with the f ring (per-level f loads were slower), and not for the
+    // plain FP32 depth-4 pass.  In edge tiles they load from clamped
+    // addresses and reset the ghost sites next to the interior once per step.
+    constexpr bool ROWS = VX == 1 && TB >= 3 && (!HAS_F || (RING && TB >= 5)) &&
+                          !(sizeof(T) == 4 && TB == 4 && !RB);
+    constexpr bool GHOST_RESET = ROWS && EDGE;
+    constexpr bool CLAMPED = GHOST_RESET;
 
     // ---- tile geometry (padded coordinates) ----
     const int ox0 = h + tx * A.ow;
@@ -198,12 +208,26 @@ __device__ __forceinline__ void jacobi_tile(const JacArgs<T> &A, int tx, int ty,
     }
     // element offset of (row r, x0) within a plane; rows outside the array are
     // never dereferenced (EDGE masks), so clamping them keeps offsets sane.
+    // With CLAMPED the x offset is clamped too: lanes whose x lies inside the
+    // array (all that load, store or are masked loads' targets) keep theirs.
     int rowoff[RY];
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
         int y = y0 + r;
         if (EDGE) y = min(max(y, 0), A.ny + 2 * h - 1);
-        rowoff[r] = y * (int)A.px + x0;
+        rowoff[r] = y * (int)A.px + (CLAMPED ? min(max(x0, 0), (int)A.px - 1) : x0);
+    }
+    // the ghost column / rows adjacent to the interior (GHOST_RESET)
+    unsigned gxm = 0, gym = 0;
+#pragma unroll
+    for (int v = 0; v < VX; ++v) {
+        const int x = x0 + v;
+        gxm |= (x == h - 1 || x == h + A.nx) ? (1u << v) : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        const int y = y0 + r;
+        gym |= (y == h - 1 || y == h + A.ny) ? (1u << r) : 0u;
     }
 
     auto load_plane = [&](int z, T (&out)[RY][VX]) {
@@ -440,17 +464,214 @@ __device__ __forceinline__ void jacobi_tile(const JacArgs<T> &A, int tx, int ty,
         exchange(buf, Bb);
     };
 
+    // Row-major steady-state step (TB >= 2): every level produces an
+    // in-range plane and the next plane exists.  For one row at a time it
+    // first forms, for every level, the partial sum up to the z- term --
+    // these read only planes of the previous step -- and then completes the
+    // levels bottom up: level tau adds the new plane of level tau-1 (z+) and
+    // writes its own new plane straight into the register of the z- plane it
+    // has just consumed.  The arithmetic and its order are those of `step`;
+    // what changes is that the plane rotation needs no register copies (the
+    // level-major step keeps a new plane in a temporary until the level
+    // above has read the plane it replaces).
+    //
+    // Edge tiles: within a step a site reads other sites only in planes of
+    // the previous step (the new plane of the level below is read at the
+    // same site), so the ghost sites next to the interior -- the only ones
+    // whose values reach an interior site -- are reset to the level below
+    // once, at the end of the step, instead of masking every update.  Sites
+    // farther out, loaded from clamped addresses, hold values nothing stored
+    // depends on.
+    auto step_rows = [&](int s, T (&Aa)[TB][RY][VX], T (&Bb)[TB][RY][VX],
+                         T (&Fc)[FPRE ? RY : 1][VX], T (&Fn)[FPRE ? RY : 1][VX]) {
+        const int rbp = RB ? ((x0 + y0 + s + 1 - 3 * h) & 1) : 0;
+        // plane s of level 0 (loaded one step early); plane s+1 is loaded now
+        T in0[RY][VX];
+#pragma unroll
+        for (int r = 0; r < RY; ++r)
+#pragma unroll
+            for (int v = 0; v < VX; ++v) in0[r][v] = nxt[r][v];
+        if constexpr (CLAMPED) {
+            const T *base = A.src + (int64_t)(s + 1) * A.plane;
+#pragma unroll
+            for (int r = 0; r < RY; ++r) nxt[r][0] = base[rowoff[r]];
+        } else {
+            load_plane(s + 1, nxt);
+        }
+        if constexpr (FPRE) load_f(s, Fn);  // for level 1 at step s+1
+        const int p_out = s - TB;
+        const bool pin = p_out >= z0 && p_out < z1;
+        const int nrec = (int)(A.plane * (int64_t)sizeof(T));
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            A.dst + (int64_t)(pin ? p_out : z0) * A.plane, 0, nrec, 0x00020000);
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            T part[TB][VX];
+#pragma unroll
+            for (int tau = 1; tau <= TB; ++tau) {
+                const T lft = from_lower_lane(Aa[tau - 1][r][VX - 1]);
+                const T rgt = from_upper_lane(Aa[tau - 1][r][0]);
+#pragma unroll
+                for (int v = 0; v < VX; ++v) {
+                    const T xm = (v > 0) ? Aa[tau - 1][r][v - 1] : lft;
+                    const T xp = (v < VX - 1) ? Aa[tau - 1][r][v + 1] : rgt;
+                    T ym, yp;
+                    if (r > 0) {
+                        ym = Aa[tau - 1][r - 1][v];
+                    } else if constexpr (NW > 1) {
+                        ym = xch[buf][tau - 1][w > 0 ? w - 1 : w][1][lane * VX + v];
+                    } else {
+                        ym = Aa[tau - 1][0][v];
+                    }
+                    if (r < RY - 1) {
+                        yp = Aa[tau - 1][r + 1][v];
+                    } else if constexpr (NW > 1) {
+                        yp = xch[buf][tau - 1][w < NW - 1 ? w + 1 : w][0][lane * VX + v];
+                    } else {
+                        yp = Aa[tau - 1][RY - 1][v];
+                    }
+                    part[tau - 1][v] = (((xm + xp) + ym) + yp) + Bb[tau - 1][r][v];
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < VX; ++v) Bb[0][r][v] = in0[r][v];
+            T outv[VX];
+#pragma unroll
+            for (int tau = 1; tau <= TB; ++tau) {
+                T fv[VX];
+                if constexpr (HAS_F) {
+                    if (FPRE && tau == 1) {
+#pragma unroll
+                        for (int v = 0; v < VX; ++v) fv[v] = Fc[FPRE ? r : 0][v];
+                    } else if constexpr (RING) {
+                        const int sl = ring_slot(s - tau);
+#pragma unroll
+                        for (int v = 0; v < VX; ++v) fv[v] = ring_at(sl, r, v);
+                    } else {
+                        const int y = EDGE ? min(max(y0 + r, h), h + A.ny - 1) : y0 + r;
+                        const unsigned ok = (updy >> r & 1u) ? updx : 0u;
+                        load_row<T, VX, EDGE>(
+                            A.f + ((int64_t)(s - tau - h) * A.ny + (y - h)) * A.nx + (x0 - h), ok,
+                            fv);
+                    }
+                }
+#pragma unroll
+                for (int v = 0; v < VX; ++v) {
+                    const T c = Aa[tau - 1][r][v];
+                    const T sum = part[tau - 1][v] + Bb[tau - 1][r][v];
+                    T val;
+                    if constexpr (HAS_A)
+                        val = (A.a * c) + (A.b * sum);
+                    else
+                        val = A.b * sum;
+                    if constexpr (HAS_F) val = val + (A.g * fv[v]);
+                    if constexpr (RB) val = ((rbp + r + v) & 1) ? c : val;
+                    if constexpr (EDGE && !GHOST_RESET) {
+                        const bool up = (updy >> r & 1u) && (updx >> v & 1u);
+                        val = up ? val : c;
+                    }
+                    if (tau < TB)
+                        Bb[tau < TB ? tau : 0][r][v] = val;
+                    else
+                        outv[v] = val;
+                }
+            }
+            // store row r of level TB (plane s-TB), as in `step`
+            if constexpr (BUF_STORE) {
+                const bool ok = pin && (sty >> r & 1u) && (stx & 1u);
+                const int off = ok ? rowoff[r] * (int)sizeof(T) : nrec;
+                if constexpr (sizeof(T) == 8)
+                    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U32x2, outv[0]), rs,
+                                                          off, 0, 0);
+                else
+                    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, outv[0]),
+                                                          rs, off, 0, 0);
+            } else if (pin && (sty >> r & 1u)) {
+                store_row<T, VX>(A.dst + (int64_t)p_out * A.plane + rowoff[r], stx, outv);
+            }
+            // keep the scheduler from interleaving rows: the rows' partial
+            // sums would then be live together and spill
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if constexpr (GHOST_RESET) {
+            // levels 1..TB-1 keep their new plane (level TB's is only stored)
+            if (gxm) {
+                __asm__ volatile("" ::: "memory");  // keep this a masked region
+#pragma unroll
+                for (int k = 1; k < TB; ++k)
+#pragma unroll
+                    for (int r = 0; r < RY; ++r)
+#pragma unroll
+                        for (int v = 0; v < VX; ++v)
+                            if (gxm >> v & 1u) Bb[k][r][v] = Aa[k - 1][r][v];
+            }
+            if (gym) {
+#pragma unroll
+                for (int r = 0; r < RY; ++r)
+                    if (gym >> r & 1u) {
+                        __asm__ volatile("" ::: "memory");
+#pragma unroll
+                        for (int k = 1; k < TB; ++k)
+#pragma unroll
+                            for (int v = 0; v < VX; ++v) Bb[k][r][v] = Aa[k - 1][r][v];
+                    }
+            }
+        }
+        if constexpr (RING) {
+            const int sl = ring_slot(s - 1);
+#pragma unroll
+            for (int r = 0; r < RY; ++r)
+#pragma unroll
+                for (int v = 0; v < VX; ++v) ring_at(sl, r, v) = Fc[r][v];
+        }
+        buf ^= 1;
+        exchange(buf, Bb);
+    };
+
     using Part = std::integral_constant<bool, false>;
     // Drain the prologue's loads here (vmcnt(0); expcnt and lgkmcnt left at
     // their maxima): otherwise the loop header has to assume them pending and
     // waits for every outstanding store on each iteration.
     __builtin_amdgcn_s_waitcnt(0x0F70);
     int s = zb + 1;
-    for (; s + 1 <= s_end; s += 2) {
-        step(s, P0, P1, F0, F1, Part{});
-        step(s + 1, P1, P0, F1, F0, Part{});
+    // last step that may load the next plane: below the top ghost plane, or
+    // anywhere in a chunk whose warm-up end lies inside the grid (plane ze+1
+    // exists there)
+    const int last_full = top_bnd ? ze - 1 : s_end;
+    if constexpr (ROWS) {
+        // Fill steps zb+1 .. zb+FILL (TB rounded up to even, so the loops
+        // below start with P0 holding the newest planes), straight-line: at
+        // step zb+k level k produces plane zb, which must keep the value of
+        // the level below (the ghost plane, or a warm-up plane no stored
+        // output depends on); the other levels produce planes below zb,
+        // never read by a plane above it.  So these are full steps whose
+        // level k is reset to level k-1 afterwards.  Then full steps while
+        // the next plane exists, and checked steps for the rest (the top
+        // ghost plane) or for chunks too short for the fill.
+        // variant A: old checked steps for fill and tail
+        const int full_lo = zb + 1 + TB;
+        if (full_lo + 1 <= last_full) {
+            for (; s < full_lo; s += 2) {
+                step(s, P0, P1, F0, F1, Part{});
+                step(s + 1, P1, P0, F1, F0, Part{});
+            }
+            for (; s + 1 <= last_full; s += 2) {
+                step_rows(s, P0, P1, F0, F1);
+                step_rows(s + 1, P1, P0, F1, F0);
+            }
+        }
+        for (; s + 1 <= s_end; s += 2) {
+            step(s, P0, P1, F0, F1, Part{});
+            step(s + 1, P1, P0, F1, F0, Part{});
+        }
+        if (s <= s_end) step(s, P0, P1, F0, F1, Part{});
+    } else {
+        for (; s + 1 <= s_end; s += 2) {
+            step(s, P0, P1, F0, F1, Part{});
+            step(s + 1, P1, P0, F1, F0, Part{});
+        }
+        if (s <= s_end) step(s, P0, P1, F0, F1, Part{});
     }
-    if (s <= s_end) step(s, P0, P1, F0, F1, Part{});
 }
 
 // A tile takes the unmasked path when its whole loaded footprint (the stored
