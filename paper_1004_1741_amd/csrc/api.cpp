@@ -122,15 +122,14 @@ int run_jacobi(const Geom &g, bool fp32, void *u, void *scratch, const void *f, 
     return ST_OK;
 }
 
-// Red-black sweeps per pass: at most 4 (8 levels on chip).  Automatic: 2
-// (4 levels).  512^3 on MI355X, us per pass at 1/2/3/4 sweeps per pass: FP64
-// 502/514/758/1235, FP32 345/305/453/689.  Three per pass ties two per sweep
-// but splits 32-sweep rounds unevenly (10 passes of 3 and two of 1); with a
-// right-hand side only 4 levels keep the f ring in LDS.
+// Red-black sweeps per pass: at most 4 (8 levels on chip).  Automatic: FP64
+// 2, FP32 3.  512^3 on MI355X, 32 sweeps with a right-hand side (the inner
+// solve of the refinement) at 1/2/3/4 sweeps per pass: FP64 23.3/14.4/23.2/
+// 35.8 ms, FP32 17.6/11.6/8.1/9.9 ms; without one, 100 sweeps: FP64 50.2/
+// 25.2/25.3/30.8 ms, FP32 2 and 3 per pass within 1 %.
 int rb_sweeps_per_pass(int t_fuse, bool fp32, bool rhs) {
     (void)rhs;
-    (void)fp32;
-    int t = t_fuse == 0 ? 2 : t_fuse;
+    int t = t_fuse == 0 ? (fp32 ? 3 : 2) : t_fuse;
     return t > 4 ? 4 : t;
 }
 
