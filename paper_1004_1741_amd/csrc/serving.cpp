@@ -249,7 +249,6 @@ hipError_t run_iteration(smooth_ctx *c, const std::vector<Job *> &act, int64_t b
     hipStream_t s = c->s_comp;
     for (Job *j : act) {
         const double a = j->spec.weights.center, b = j->spec.weights.neighbor;
-        const bool ha = a != 0.0;
         hipError_t e = hipSuccess;  // this job's set-up only
         if (j->ph == PH_READY) {
             j->st.t_start_ns = now_ns();
