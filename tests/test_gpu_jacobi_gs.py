@@ -63,6 +63,8 @@ JAC_CASES = [
     (119, 24, 40, 1, 8),    # x: two FP64 t=4 tiles of 56 and a ragged 7
     (245, 50, 19, 1, 13),
     (300, 70, 33, 1, 17),   # several tiles in x and y, several z-chunks
+    (70, 61, 30, 3, 11),    # three ghost layers, boundary tiles on all sides,
+                            # chunks long enough for steady-state steps
 ]
 
 
