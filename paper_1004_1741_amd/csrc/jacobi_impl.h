@@ -464,7 +464,7 @@ __device__ __forceinline__ void jacobi_tile(const JacArgs<T> &A, int tx, int ty,
         exchange(buf, Bb);
     };
 
-    // Row-major steady-state step (TB >= 2): every level produces an
+    // Row-major steady-state step (ROWS): every level produces an
     // in-range plane and the next plane exists.  For one row at a time it
     // first forms, for every level, the partial sum up to the z- term --
     // these read only planes of the previous step -- and then completes the
@@ -639,16 +639,15 @@ __device__ __forceinline__ void jacobi_tile(const JacArgs<T> &A, int tx, int ty,
     // exists there)
     const int last_full = top_bnd ? ze - 1 : s_end;
     if constexpr (ROWS) {
-        // Fill steps zb+1 .. zb+FILL (TB rounded up to even, so the loops
-        // below start with P0 holding the newest planes), straight-line: at
-        // step zb+k level k produces plane zb, which must keep the value of
-        // the level below (the ghost plane, or a warm-up plane no stored
-        // output depends on); the other levels produce planes below zb,
-        // never read by a plane above it.  So these are full steps whose
-        // level k is reset to level k-1 afterwards.  Then full steps while
-        // the next plane exists, and checked steps for the rest (the top
-        // ghost plane) or for chunks too short for the fill.
-        // variant A: old checked steps for fill and tail
+        // Three loops over pairs of steps (the planes alternate between P0
+        // and P1, so every loop starts with P0 holding the newest planes):
+        // checked level-major steps while the pipeline fills (some level's
+        // plane still lies below zb+1), row-major steady-state steps while
+        // every level is in range and the next plane exists, checked steps
+        // for the rest (the top ghost plane).  Chunks too short for a
+        // steady pair use checked steps throughout.  Each loop keeps to one
+        // kind of step: a loop choosing between the two made the register
+        // allocator spill.
         const int full_lo = zb + 1 + TB;
         if (full_lo + 1 <= last_full) {
             for (; s < full_lo; s += 2) {
