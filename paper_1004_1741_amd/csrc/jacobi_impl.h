@@ -138,6 +138,135 @@ struct FRing {
     static constexpr size_t alloc = on ? ring_elems : 1;
 };
 
+// Ghost reset of one row: on the lanes of `mask` (all lanes for a ghost row,
+// the ghost-column lanes otherwise, none for most rows) level k's new plane
+// takes the value of level k-1, for k = 1..TB-1.  The exec mask and the skip
+// branch live inside one asm statement, so the compiler sees in-place updates
+// only: with the branch at the source level the register allocator changed
+// the steady loop's register assignment and copied the prefetched plane at
+// the loop's back edge, waiting there for loads issued one step earlier.
+template <typename T, int TB, int RY, int VX>
+__device__ __forceinline__ void ghost_reset_row(T (&Bb)[TB][RY][VX], const T (&Aa)[TB][RY][VX],
+                                                int r, unsigned long long mask) {
+    static_assert(TB >= 3 && TB <= 8 && VX == 1, "ghost reset: 3..8 levels, one site per lane");
+    unsigned long long sv;
+#define GR_HEAD "s_and_saveexec_b64 %[sv], %[m]\n\ts_cbranch_execz 1f\n\t"
+#define GR_TAIL "1:\n\ts_mov_b64 exec, %[sv]"
+    if constexpr (sizeof(T) == 8) {
+#define GR_M(d, s) "v_mov_b64 %[" #d "], %[" #s "]\n\t"
+        if constexpr (TB == 3) {
+            __asm__ volatile(GR_HEAD GR_M(d1, s1) GR_M(d2, s2) GR_TAIL
+                             : [d1] "+v"(Bb[1][r][0]), [d2] "+v"(Bb[2][r][0]), [sv] "=&s"(sv)
+                             : [s1] "v"(Aa[0][r][0]), [s2] "v"(Aa[1][r][0]), [m] "s"(mask)
+                             : "scc");
+        } else if constexpr (TB == 4) {
+            __asm__ volatile(GR_HEAD GR_M(d1, s1) GR_M(d2, s2) GR_M(d3, s3) GR_TAIL
+                             : [d1] "+v"(Bb[1][r][0]), [d2] "+v"(Bb[2][r][0]),
+                               [d3] "+v"(Bb[3][r][0]), [sv] "=&s"(sv)
+                             : [s1] "v"(Aa[0][r][0]), [s2] "v"(Aa[1][r][0]),
+                               [s3] "v"(Aa[2][r][0]), [m] "s"(mask)
+                             : "scc");
+        } else if constexpr (TB == 5) {
+            __asm__ volatile(GR_HEAD GR_M(d1, s1) GR_M(d2, s2) GR_M(d3, s3) GR_M(d4, s4) GR_TAIL
+                             : [d1] "+v"(Bb[1][r][0]), [d2] "+v"(Bb[2][r][0]),
+                               [d3] "+v"(Bb[3][r][0]), [d4] "+v"(Bb[4][r][0]), [sv] "=&s"(sv)
+                             : [s1] "v"(Aa[0][r][0]), [s2] "v"(Aa[1][r][0]),
+                               [s3] "v"(Aa[2][r][0]), [s4] "v"(Aa[3][r][0]), [m] "s"(mask)
+                             : "scc");
+        } else if constexpr (TB == 6) {
+            __asm__ volatile(GR_HEAD GR_M(d1, s1) GR_M(d2, s2) GR_M(d3, s3) GR_M(d4, s4)
+                                 GR_M(d5, s5) GR_TAIL
+                             : [d1] "+v"(Bb[1][r][0]), [d2] "+v"(Bb[2][r][0]),
+                               [d3] "+v"(Bb[3][r][0]), [d4] "+v"(Bb[4][r][0]),
+                               [d5] "+v"(Bb[5][r][0]), [sv] "=&s"(sv)
+                             : [s1] "v"(Aa[0][r][0]), [s2] "v"(Aa[1][r][0]),
+                               [s3] "v"(Aa[2][r][0]), [s4] "v"(Aa[3][r][0]),
+                               [s5] "v"(Aa[4][r][0]), [m] "s"(mask)
+                             : "scc");
+        } else if constexpr (TB == 7) {
+            __asm__ volatile(GR_HEAD GR_M(d1, s1) GR_M(d2, s2) GR_M(d3, s3) GR_M(d4, s4)
+                                 GR_M(d5, s5) GR_M(d6, s6) GR_TAIL
+                             : [d1] "+v"(Bb[1][r][0]), [d2] "+v"(Bb[2][r][0]),
+                               [d3] "+v"(Bb[3][r][0]), [d4] "+v"(Bb[4][r][0]),
+                               [d5] "+v"(Bb[5][r][0]), [d6] "+v"(Bb[6][r][0]), [sv] "=&s"(sv)
+                             : [s1] "v"(Aa[0][r][0]), [s2] "v"(Aa[1][r][0]),
+                               [s3] "v"(Aa[2][r][0]), [s4] "v"(Aa[3][r][0]),
+                               [s5] "v"(Aa[4][r][0]), [s6] "v"(Aa[5][r][0]), [m] "s"(mask)
+                             : "scc");
+        } else if constexpr (TB == 8) {
+            __asm__ volatile(GR_HEAD GR_M(d1, s1) GR_M(d2, s2) GR_M(d3, s3) GR_M(d4, s4)
+                                 GR_M(d5, s5) GR_M(d6, s6) GR_M(d7, s7) GR_TAIL
+                             : [d1] "+v"(Bb[1][r][0]), [d2] "+v"(Bb[2][r][0]),
+                               [d3] "+v"(Bb[3][r][0]), [d4] "+v"(Bb[4][r][0]),
+                               [d5] "+v"(Bb[5][r][0]), [d6] "+v"(Bb[6][r][0]),
+                               [d7] "+v"(Bb[7][r][0]), [sv] "=&s"(sv)
+                             : [s1] "v"(Aa[0][r][0]), [s2] "v"(Aa[1][r][0]),
+                               [s3] "v"(Aa[2][r][0]), [s4] "v"(Aa[3][r][0]),
+                               [s5] "v"(Aa[4][r][0]), [s6] "v"(Aa[5][r][0]),
+                               [s7] "v"(Aa[6][r][0]), [m] "s"(mask)
+                             : "scc");
+        }
+#undef GR_M
+    } else {
+#define GR_M(d, s) "v_mov_b32 %[" #d "], %[" #s "]\n\t"
+        if constexpr (TB == 3) {
+            __asm__ volatile(GR_HEAD GR_M(d1, s1) GR_M(d2, s2) GR_TAIL
+                             : [d1] "+v"(Bb[1][r][0]), [d2] "+v"(Bb[2][r][0]), [sv] "=&s"(sv)
+                             : [s1] "v"(Aa[0][r][0]), [s2] "v"(Aa[1][r][0]), [m] "s"(mask)
+                             : "scc");
+        } else if constexpr (TB == 4) {
+            __asm__ volatile(GR_HEAD GR_M(d1, s1) GR_M(d2, s2) GR_M(d3, s3) GR_TAIL
+                             : [d1] "+v"(Bb[1][r][0]), [d2] "+v"(Bb[2][r][0]),
+                               [d3] "+v"(Bb[3][r][0]), [sv] "=&s"(sv)
+                             : [s1] "v"(Aa[0][r][0]), [s2] "v"(Aa[1][r][0]),
+                               [s3] "v"(Aa[2][r][0]), [m] "s"(mask)
+                             : "scc");
+        } else if constexpr (TB == 5) {
+            __asm__ volatile(GR_HEAD GR_M(d1, s1) GR_M(d2, s2) GR_M(d3, s3) GR_M(d4, s4) GR_TAIL
+                             : [d1] "+v"(Bb[1][r][0]), [d2] "+v"(Bb[2][r][0]),
+                               [d3] "+v"(Bb[3][r][0]), [d4] "+v"(Bb[4][r][0]), [sv] "=&s"(sv)
+                             : [s1] "v"(Aa[0][r][0]), [s2] "v"(Aa[1][r][0]),
+                               [s3] "v"(Aa[2][r][0]), [s4] "v"(Aa[3][r][0]), [m] "s"(mask)
+                             : "scc");
+        } else if constexpr (TB == 6) {
+            __asm__ volatile(GR_HEAD GR_M(d1, s1) GR_M(d2, s2) GR_M(d3, s3) GR_M(d4, s4)
+                                 GR_M(d5, s5) GR_TAIL
+                             : [d1] "+v"(Bb[1][r][0]), [d2] "+v"(Bb[2][r][0]),
+                               [d3] "+v"(Bb[3][r][0]), [d4] "+v"(Bb[4][r][0]),
+                               [d5] "+v"(Bb[5][r][0]), [sv] "=&s"(sv)
+                             : [s1] "v"(Aa[0][r][0]), [s2] "v"(Aa[1][r][0]),
+                               [s3] "v"(Aa[2][r][0]), [s4] "v"(Aa[3][r][0]),
+                               [s5] "v"(Aa[4][r][0]), [m] "s"(mask)
+                             : "scc");
+        } else if constexpr (TB == 7) {
+            __asm__ volatile(GR_HEAD GR_M(d1, s1) GR_M(d2, s2) GR_M(d3, s3) GR_M(d4, s4)
+                                 GR_M(d5, s5) GR_M(d6, s6) GR_TAIL
+                             : [d1] "+v"(Bb[1][r][0]), [d2] "+v"(Bb[2][r][0]),
+                               [d3] "+v"(Bb[3][r][0]), [d4] "+v"(Bb[4][r][0]),
+                               [d5] "+v"(Bb[5][r][0]), [d6] "+v"(Bb[6][r][0]), [sv] "=&s"(sv)
+                             : [s1] "v"(Aa[0][r][0]), [s2] "v"(Aa[1][r][0]),
+                               [s3] "v"(Aa[2][r][0]), [s4] "v"(Aa[3][r][0]),
+                               [s5] "v"(Aa[4][r][0]), [s6] "v"(Aa[5][r][0]), [m] "s"(mask)
+                             : "scc");
+        } else if constexpr (TB == 8) {
+            __asm__ volatile(GR_HEAD GR_M(d1, s1) GR_M(d2, s2) GR_M(d3, s3) GR_M(d4, s4)
+                                 GR_M(d5, s5) GR_M(d6, s6) GR_M(d7, s7) GR_TAIL
+                             : [d1] "+v"(Bb[1][r][0]), [d2] "+v"(Bb[2][r][0]),
+                               [d3] "+v"(Bb[3][r][0]), [d4] "+v"(Bb[4][r][0]),
+                               [d5] "+v"(Bb[5][r][0]), [d6] "+v"(Bb[6][r][0]),
+                               [d7] "+v"(Bb[7][r][0]), [sv] "=&s"(sv)
+                             : [s1] "v"(Aa[0][r][0]), [s2] "v"(Aa[1][r][0]),
+                               [s3] "v"(Aa[2][r][0]), [s4] "v"(Aa[3][r][0]),
+                               [s5] "v"(Aa[4][r][0]), [s6] "v"(Aa[5][r][0]),
+                               [s7] "v"(Aa[6][r][0]), [m] "s"(mask)
+                             : "scc");
+        }
+#undef GR_M
+    }
+#undef GR_HEAD
+#undef GR_TAIL
+}
+
 // RB: red-black Gauss-Seidel.  Level tau updates only the sites of colour
 // (tau - 1) & 1 (colour = parity of (x-h) + (y-h) + (z-h)) and copies the
 // others from level tau-1; axis neighbours have the other colour, so two
@@ -164,12 +293,18 @@ __device__ __forceinline__ void jacobi_tile(const JacArgs<T> &A, int tx, int ty,
     // MI355X at 512^3: tiles of one site per lane (two per lane were slower),
     // three or more levels, with a right-hand side only from five levels up
     // and with the f ring (per-level f loads were slower), and not for the
-    // plain FP32 depth-4 pass.  In edge tiles they load from clamped
-    // addresses and reset the ghost sites next to the interior once per step.
+    // plain FP32 depth-4 pass.  In edge tiles they reset the ghost sites next
+    // to the interior once per step (GHOST_RESET).  From five levels in FP64
+    // and six in FP32 (EDGE_ASM) edge tiles load through buffer loads that
+    // return 0 for sites outside the array and do the reset in asm without
+    // compiler-visible branches; below that, loads from clamped addresses and
+    // a branch per reset measured faster (FP64 t=3/4 by 2-3 %, FP32 t=5 by 2 %).
     constexpr bool ROWS = VX == 1 && TB >= 3 && (!HAS_F || (RING && TB >= 5)) &&
                           !(sizeof(T) == 4 && TB == 4 && !RB);
     constexpr bool GHOST_RESET = ROWS && EDGE;
-    constexpr bool CLAMPED = GHOST_RESET;
+    constexpr bool EDGE_ASM = GHOST_RESET && TB >= (sizeof(T) == 8 ? 5 : 6);
+    constexpr bool EDGE_BUF_LOAD = EDGE_ASM;
+    constexpr bool CLAMPED = GHOST_RESET && !EDGE_ASM;
 
     // ---- tile geometry (padded coordinates) ----
     const int ox0 = h + tx * A.ow;
@@ -208,16 +343,22 @@ __device__ __forceinline__ void jacobi_tile(const JacArgs<T> &A, int tx, int ty,
     }
     // element offset of (row r, x0) within a plane; rows outside the array are
     // never dereferenced (EDGE masks), so clamping them keeps offsets sane.
-    // With CLAMPED the x offset is clamped too: lanes whose x lies inside the
-    // array (all that load, store or are masked loads' targets) keep theirs.
+    // With EDGE_BUF_LOAD a site outside the array gets the offset of the next
+    // plane instead, which a buffer load of this plane treats as out of range
+    // (it returns 0 without a memory access); sites inside the array (all
+    // that load, store or are masked loads' targets) keep their offset.
+    // With CLAMPED the x offset is clamped instead, so that an unmasked load
+    // stays inside the array.
     int rowoff[RY];
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
         int y = y0 + r;
         if (EDGE) y = min(max(y, 0), A.ny + 2 * h - 1);
         rowoff[r] = y * (int)A.px + (CLAMPED ? min(max(x0, 0), (int)A.px - 1) : x0);
+        if (EDGE_BUF_LOAD && !((ldy >> r & 1u) && (ldx & 1u))) rowoff[r] = (int)A.plane;
     }
-    // the ghost column / rows adjacent to the interior (GHOST_RESET)
+    // the ghost column / rows adjacent to the interior (GHOST_RESET): the
+    // lanes holding the column, and per wave the rows that are ghost rows
     unsigned gxm = 0, gym = 0;
 #pragma unroll
     for (int v = 0; v < VX; ++v) {
@@ -229,6 +370,8 @@ __device__ __forceinline__ void jacobi_tile(const JacArgs<T> &A, int tx, int ty,
         const int y = y0 + r;
         gym |= (y == h - 1 || y == h + A.ny) ? (1u << r) : 0u;
     }
+    gym = __builtin_amdgcn_readfirstlane(gym);
+    const unsigned long long gx_lanes = __builtin_amdgcn_ballot_w64(gxm != 0u);
 
     auto load_plane = [&](int z, T (&out)[RY][VX]) {
         const T *base = A.src + (int64_t)z * A.plane;
@@ -491,7 +634,21 @@ __device__ __forceinline__ void jacobi_tile(const JacArgs<T> &A, int tx, int ty,
         for (int r = 0; r < RY; ++r)
 #pragma unroll
             for (int v = 0; v < VX; ++v) in0[r][v] = nxt[r][v];
-        if constexpr (CLAMPED) {
+        if constexpr (EDGE_BUF_LOAD) {
+            const __amdgpu_buffer_rsrc_t rl = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<T *>(A.src) + (int64_t)(s + 1) * A.plane, 0,
+                (int)(A.plane * (int64_t)sizeof(T)), 0x00020000);
+#pragma unroll
+            for (int r = 0; r < RY; ++r) {
+                const int off = rowoff[r] * (int)sizeof(T);
+                if constexpr (sizeof(T) == 8)
+                    nxt[r][0] = __builtin_bit_cast(
+                        T, __builtin_amdgcn_raw_buffer_load_b64(rl, off, 0, 0));
+                else
+                    nxt[r][0] = __builtin_bit_cast(
+                        T, __builtin_amdgcn_raw_buffer_load_b32(rl, off, 0, 0));
+            }
+        } else if constexpr (CLAMPED) {
             const T *base = A.src + (int64_t)(s + 1) * A.plane;
 #pragma unroll
             for (int r = 0; r < RY; ++r) nxt[r][0] = base[rowoff[r]];
@@ -593,17 +750,19 @@ __device__ __forceinline__ void jacobi_tile(const JacArgs<T> &A, int tx, int ty,
             // sums would then be live together and spill
             __builtin_amdgcn_sched_barrier(0);
         }
-        if constexpr (GHOST_RESET) {
-            // levels 1..TB-1 keep their new plane (level TB's is only stored)
+        // levels 1..TB-1 keep their new plane (level TB's is only stored)
+        if constexpr (EDGE_ASM) {
+#pragma unroll
+            for (int r = 0; r < RY; ++r)
+                ghost_reset_row<T, TB, RY, VX>(Bb, Aa, r, (gym >> r & 1u) ? ~0ull : gx_lanes);
+        } else if constexpr (GHOST_RESET) {
             if (gxm) {
                 __asm__ volatile("" ::: "memory");  // keep this a masked region
 #pragma unroll
                 for (int k = 1; k < TB; ++k)
 #pragma unroll
                     for (int r = 0; r < RY; ++r)
-#pragma unroll
-                        for (int v = 0; v < VX; ++v)
-                            if (gxm >> v & 1u) Bb[k][r][v] = Aa[k - 1][r][v];
+                        Bb[k][r][0] = Aa[k - 1][r][0];
             }
             if (gym) {
 #pragma unroll
@@ -611,9 +770,7 @@ __device__ __forceinline__ void jacobi_tile(const JacArgs<T> &A, int tx, int ty,
                     if (gym >> r & 1u) {
                         __asm__ volatile("" ::: "memory");
 #pragma unroll
-                        for (int k = 1; k < TB; ++k)
-#pragma unroll
-                            for (int v = 0; v < VX; ++v) Bb[k][r][v] = Aa[k - 1][r][v];
+                        for (int k = 1; k < TB; ++k) Bb[k][r][0] = Aa[k - 1][r][0];
                     }
             }
         }
@@ -897,7 +1054,8 @@ hipError_t launch_batch_t(const std::vector<JacBatchItem> &items, void *table_de
     int total = 0;
     for (size_t j = 0; j < items.size(); ++j) {
         const JacBatchItem &it = items[j];
-        jobs[j].a = make_args<T, TB, HAS_F>(it.g, it.src, it.dst, it.f, it.a, it.b, it.gw, 0, resident);
+        jobs[j].a =
+            make_args<T, TB, HAS_F>(it.g, it.src, it.dst, it.f, it.a, it.b, it.gw, 0, resident);
         jobs[j].wg_begin = total;
         total += jobs[j].a.ntiles;
     }
