@@ -623,8 +623,8 @@ __device__ __forceinline__ void jacobi_tile(const JacArgs<T> &A, int tx, int ty,
     // same site), so the ghost sites next to the interior -- the only ones
     // whose values reach an interior site -- are reset to the level below
     // once, at the end of the step, instead of masking every update.  Sites
-    // farther out, loaded from clamped addresses, hold values nothing stored
-    // depends on.
+    // farther out (loaded as 0 by out-of-range buffer loads, or from clamped
+    // addresses) hold values nothing stored depends on.
     auto step_rows = [&](int s, T (&Aa)[TB][RY][VX], T (&Bb)[TB][RY][VX],
                          T (&Fc)[FPRE ? RY : 1][VX], T (&Fn)[FPRE ? RY : 1][VX]) {
         const int rbp = RB ? ((x0 + y0 + s + 1 - 3 * h) & 1) : 0;
