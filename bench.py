@@ -7,7 +7,8 @@ One *step* is the headline workload: 100 FP64 Jacobi sweeps on a 512^3
 interior (ghost and interior values U[0,1), a = 0, b = 1/6), fused t sweeps
 per pass over HBM (t chosen by the library unless --t is given).  The value is
 MLUP/s = 512^3 * 100 * K / (time of K steps); inputs are resident in HBM
-before the timed region.  Extra fields report every t, FP32 storage, the
+before the timed region.  Defaults: K = 20 timed steps after W = 10 untimed
+ones (about 0.1 s of warm-up, enough for the clocks to settle).  Extra fields report every t, FP32 storage, the
 Gauss-Seidel wavefront on 384^3 x 50, the FP32-refined vs plain FP64 Poisson
 solve, and the serving stream, each measured after the headline.
 
@@ -115,8 +116,8 @@ def log(*a):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--sweeps", type=int, default=100)
     ap.add_argument("--t", type=int, default=0, help="fused sweeps per pass (0 = library choice)")

@@ -63,10 +63,10 @@ int check_grid(const st_grid *g, Geom *out) {
 bool valid_t(int t) { return (t >= 0 && t <= 8) || t == 16; }
 
 // Automatic depth, measured at 512^3 on MI355X (100 sweeps; 32 with f):
-// FP64 t=5 (588 us per pass, 118 us per sweep; t=4 493 us, 123 per sweep;
-// t=6 ties per sweep but 100 is not a multiple of 6), with f t=4 (32 sweeps
-// in 8 passes; t=5 needs 8 passes too, two of them of one sweep); FP32 t=5,
-// with f t=6.
+// FP64 t=5 (559 us per pass, 112 us per sweep; t=4 481 us, 120 per sweep;
+// t=6 660 us, 110 per sweep, but 100 is not a multiple of 6), with f t=4
+// (32 sweeps in 8 passes; t=5 needs 8 passes too, two of them of one
+// sweep); FP32 t=5, with f t=6.
 int auto_t(int dtype, bool rhs) {
     if (dtype == ST_FP32) return rhs ? 6 : 5;
     return rhs ? 4 : 5;
