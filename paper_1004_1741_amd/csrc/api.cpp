@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/stencil.h"
@@ -75,15 +76,16 @@ int auto_t(int dtype, bool rhs) {
 // Pass schedule: floor(S/t) passes of t plus one pass of the remainder (every
 // depth 1..8 is compiled); if the count is odd the smallest pass with >= 2
 // sweeps is split in two so the result lands in u, else a final copy is
-// needed.
-std::vector<int> jacobi_plan(int dtype, bool rhs, int sweeps, int t_fuse, bool *final_copy) {
+// needed.  any_parity: keep an odd count (the caller swaps its grids).
+std::vector<int> jacobi_plan(int dtype, bool rhs, int sweeps, int t_fuse, bool *final_copy,
+                             bool any_parity = false) {
     int t = t_fuse == 0 ? auto_t(dtype, rhs) : t_fuse;
     if (t > 8) t = 8;  // at most 8 levels fit on chip per pass
     std::vector<int> p;
     for (int i = 0; i < sweeps / t; ++i) p.push_back(t);
     if (sweeps % t) p.push_back(sweeps % t);
     *final_copy = false;
-    if (p.size() % 2 == 1) {
+    if (p.size() % 2 == 1 && !any_parity) {
         int best = -1;
         for (size_t i = 0; i < p.size(); ++i)
             if (p[i] >= 2 && (best < 0 || p[i] < p[best])) best = (int)i;
@@ -104,22 +106,43 @@ bool overlaps(const void *a, const void *b, size_t bytes) {
     return x < y + bytes && y < x + bytes;
 }
 
-int run_jacobi(const Geom &g, bool fp32, void *u, void *scratch, const void *f, double a,
-               double b, double gw, int sweeps, int t_fuse, hipStream_t s) {
+// Red-black sweeps per pass (defined below).
+int rb_sweeps_per_pass(int t_fuse, bool fp32, bool rhs);
+
+// The fused passes of `sweeps` Jacobi (rb = false) or red-black (rb = true)
+// sweeps, alternating between *u and *scratch.  The result is returned in *u.
+// owned: the caller owns both grids and their ghost cells are equal, so an
+// odd number of passes leaves the result in the other grid and the two
+// pointers are swapped; otherwise the schedule has an even count (a pass is
+// split) or ends with a copy of the interior back to *u.
+int run_fused(bool rb, const Geom &g, bool fp32, void **u, void **scratch, bool owned,
+              const void *f, double a, double b, double gw, int sweeps, int t_fuse,
+              hipStream_t s) {
     if (sweeps == 0) return ST_OK;
     bool fc = false;
-    std::vector<int> plan = jacobi_plan(fp32 ? ST_FP32 : ST_FP64, f != nullptr, sweeps, t_fuse, &fc);
-    HIP_TRY(launch_copy_ghosts(fp32, g, u, scratch, s), "ghost copy");
-    const void *src = u;
-    void *dst = scratch;
-    for (int tb : plan) {
-        HIP_TRY(launch_jacobi_pass(fp32, tb, g, src, dst, f, a, b, gw, 0, s), "jacobi pass");
-        void *t = const_cast<void *>(src);
+    const int t = rb ? rb_sweeps_per_pass(t_fuse, fp32, f != nullptr) : t_fuse;
+    std::vector<int> plan =
+        jacobi_plan(fp32 ? ST_FP32 : ST_FP64, f != nullptr, sweeps, t, &fc, owned);
+    HIP_TRY(launch_copy_ghosts(fp32, g, *u, *scratch, s), "ghost copy");
+    const void *src = *u;
+    void *dst = *scratch;
+    for (int n : plan) {
+        if (rb)
+            HIP_TRY(launch_rbgs_pass(fp32, n, g, src, dst, f, a, b, gw, s), "red-black pass");
+        else
+            HIP_TRY(launch_jacobi_pass(fp32, n, g, src, dst, f, a, b, gw, 0, s), "jacobi pass");
+        void *tmp = const_cast<void *>(src);
         src = dst;
-        dst = t;
+        dst = tmp;
     }
-    if (fc) HIP_TRY(launch_copy_interior(fp32, g, scratch, u, s), "final copy");
+    if (fc) HIP_TRY(launch_copy_interior(fp32, g, *scratch, *u, s), "final copy");
+    if (owned && plan.size() % 2 == 1) std::swap(*u, *scratch);
     return ST_OK;
+}
+
+int run_jacobi(const Geom &g, bool fp32, void *u, void *scratch, const void *f, double a,
+               double b, double gw, int sweeps, int t_fuse, hipStream_t s) {
+    return run_fused(false, g, fp32, &u, &scratch, false, f, a, b, gw, sweeps, t_fuse, s);
 }
 
 // Red-black sweeps per pass: at most 4 (8 levels on chip).  Automatic: FP64
@@ -133,25 +156,10 @@ int rb_sweeps_per_pass(int t_fuse, bool fp32, bool rhs) {
     return t > 4 ? 4 : t;
 }
 
+// the same schedule rule as Jacobi, counted in red-black sweeps
 int run_rbgs(const Geom &g, bool fp32, void *u, void *scratch, const void *f, double a, double b,
              double gw, int sweeps, int t_fuse, hipStream_t s) {
-    if (sweeps == 0) return ST_OK;
-    bool fc = false;
-    // the same schedule rule as Jacobi, counted in red-black sweeps
-    std::vector<int> plan =
-        jacobi_plan(fp32 ? ST_FP32 : ST_FP64, f != nullptr, sweeps,
-                    rb_sweeps_per_pass(t_fuse, fp32, f != nullptr), &fc);
-    HIP_TRY(launch_copy_ghosts(fp32, g, u, scratch, s), "ghost copy");
-    const void *src = u;
-    void *dst = scratch;
-    for (int n : plan) {
-        HIP_TRY(launch_rbgs_pass(fp32, n, g, src, dst, f, a, b, gw, s), "red-black pass");
-        void *tmp = const_cast<void *>(src);
-        src = dst;
-        dst = tmp;
-    }
-    if (fc) HIP_TRY(launch_copy_interior(fp32, g, scratch, u, s), "final copy");
-    return ST_OK;
+    return run_fused(true, g, fp32, &u, &scratch, false, f, a, b, gw, sweeps, t_fuse, s);
 }
 
 // Sweeps in flight per wavefront launch: t_fuse, or all (at most 4095).
@@ -449,6 +457,9 @@ int stencil_refine_solve(const st_grid *grid, int32_t method, int32_t inner_dtyp
         if (sbuf.p) HIP_TRY(hipMemsetAsync(sbuf.p, 0, (size_t)np * sizeof(float), s), "memset");
     }
     const st_weights pw = {0.0, 1.0 / 6.0, 1.0 / 6.0};
+    // the FP32 correction and its scratch grid (both owned here: an odd pass
+    // count swaps them instead of splitting a pass)
+    void *e = ebuf.p, *es = sbuf.p;
     int outer = 0;
     double rel = INFINITY;
     int status = ST_ENOCONV;
@@ -467,18 +478,15 @@ int stencil_refine_solve(const st_grid *grid, int32_t method, int32_t inner_dtyp
         if (outer >= max_outer) break;
         if (f32) {
             // e = 0 (ghosts stay 0), then inner_sweeps float sweeps on A e = r
-            HIP_TRY(hipMemsetAsync(ebuf.p, 0, (size_t)np * sizeof(float), s), "memset");
-            if (method == 0)
-                rc = run_jacobi(g, true, ebuf.p, sbuf.p, rbuf.p, pw.center, pw.neighbor, pw.rhs,
-                                inner_sweeps, t_fuse, s);
-            else if (method == 2)
-                rc = run_rbgs(g, true, ebuf.p, sbuf.p, rbuf.p, pw.center, pw.neighbor, pw.rhs,
-                              inner_sweeps, t_fuse, s);
+            HIP_TRY(hipMemsetAsync(e, 0, (size_t)np * sizeof(float), s), "memset");
+            if (method == 1)
+                rc = run_gs(g, true, e, rbuf.p, pw.center, pw.neighbor, pw.rhs, inner_sweeps,
+                            t_fuse, s);
             else
-                rc = run_gs(g, true, ebuf.p, rbuf.p, pw.center, pw.neighbor, pw.rhs,
-                            inner_sweeps, t_fuse, s);
+                rc = run_fused(method == 2, g, true, &e, &es, true, rbuf.p, pw.center,
+                               pw.neighbor, pw.rhs, inner_sweeps, t_fuse, s);
             if (rc) return rc;
-            HIP_TRY(launch_correct(g, u, ebuf.p, true, s), "correct");
+            HIP_TRY(launch_correct(g, u, e, true, s), "correct");
         } else {
             // the plain FP64 method: smooth u itself with the right-hand side
             if (method == 0)
@@ -584,18 +592,22 @@ int stencil_mg_solve(const st_grid *grid, int32_t smoother, int32_t inner_dtype,
     double *partials = (double *)(base + part_off);
     double *dsum = partials + nb;
 
+    // the correction of each level and its scratch grid: an odd number of
+    // smoothing passes swaps the two instead of splitting a pass
+    std::vector<void *> e(nlev), esc(nlev);
+    for (int l = 0; l < nlev; ++l) e[l] = E(l), esc[l] = ES(l);
     auto smooth = [&](int l, int sweeps) -> int {
         if (sweeps <= 0) return ST_OK;
         if (smoother == 0)  // weighted Jacobi, omega = 6/7
-            return run_jacobi(lv[l], f32, E(l), ES(l), R(l), 1.0 / 7.0, 1.0 / 7.0, 1.0 / 7.0,
-                              sweeps, 0, s);
+            return run_fused(false, lv[l], f32, &e[l], &esc[l], true, R(l), 1.0 / 7.0, 1.0 / 7.0,
+                             1.0 / 7.0, sweeps, 0, s);
         if (smoother == 2)
-            return run_rbgs(lv[l], f32, E(l), ES(l), R(l), 0.0, 1.0 / 6.0, 1.0 / 6.0, sweeps, 0,
-                            s);
-        return run_gs(lv[l], f32, E(l), R(l), 0.0, 1.0 / 6.0, 1.0 / 6.0, sweeps, 0, s);
+            return run_fused(true, lv[l], f32, &e[l], &esc[l], true, R(l), 0.0, 1.0 / 6.0,
+                             1.0 / 6.0, sweeps, 0, s);
+        return run_gs(lv[l], f32, e[l], R(l), 0.0, 1.0 / 6.0, 1.0 / 6.0, sweeps, 0, s);
     };
     auto zero = [&](int l) {
-        return hipMemsetAsync(E(l), 0, (size_t)lv[l].count() * es, s);
+        return hipMemsetAsync(e[l], 0, (size_t)lv[l].count() * es, s);
     };
     if (smoother != 1)  // scratch ghosts start at 0 (run_jacobi / run_rbgs copy them anyway)
         for (int l = 0; l < nlev; ++l)
@@ -631,18 +643,18 @@ int stencil_mg_solve(const st_grid *grid, int32_t smoother, int32_t inner_dtype,
         for (int l = 0; l + 1 < nlev; ++l) {
             HIP_TRY(zero(l), "memset");
             if ((rc = smooth(l, pre))) return rc;
-            HIP_TRY(launch_mg_residual(f32, lv[l], E(l), R(l), RES(l), s), "mg residual");
+            HIP_TRY(launch_mg_residual(f32, lv[l], e[l], R(l), RES(l), s), "mg residual");
             HIP_TRY(launch_mg_restrict(f32, lv[l], lv[l + 1], tabs[l], RES(l), R(l + 1), s),
                     "mg restrict");
         }
         HIP_TRY(zero(nlev - 1), "memset");
         if ((rc = smooth(nlev - 1, coarse_sweeps))) return rc;
         for (int l = nlev - 2; l >= 0; --l) {
-            HIP_TRY(launch_mg_prolong(f32, lv[l], lv[l + 1], tabs[l], E(l), E(l + 1), s),
+            HIP_TRY(launch_mg_prolong(f32, lv[l], lv[l + 1], tabs[l], e[l], e[l + 1], s),
                     "mg prolong");
             if ((rc = smooth(l, post))) return rc;
         }
-        HIP_TRY(launch_correct(g, u, E(0), f32, s), "correct");
+        HIP_TRY(launch_correct(g, u, e[0], f32, s), "correct");
         ++cyc;
         if (smoother == 1) {
             rc = check_gs_status(s);
