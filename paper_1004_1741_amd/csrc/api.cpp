@@ -4,6 +4,7 @@
 // gs.hip and aux.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -575,6 +576,12 @@ int stencil_mg_solve(const st_grid *grid, int32_t smoother, int32_t inner_dtype,
             return fail(ST_EINVAL, "multigrid transfer support too wide for this grid");
     const size_t tab_off = total;
     total += up(tb.size());
+    // partial sums of the restriction (one level at a time: the largest)
+    size_t rtmp = 0;
+    for (int l = 0; l + 1 < nlev; ++l)
+        rtmp = std::max(rtmp, mg_restrict_tmp_bytes(f32, lv[l], lv[l + 1]));
+    const size_t rtmp_off = total;
+    total += up(rtmp);
     const int nb = residual_partial_count(g);
     const size_t part_off = total;
     total += up(((size_t)nb + 2) * sizeof(double));
@@ -644,7 +651,8 @@ int stencil_mg_solve(const st_grid *grid, int32_t smoother, int32_t inner_dtype,
             HIP_TRY(zero(l), "memset");
             if ((rc = smooth(l, pre))) return rc;
             HIP_TRY(launch_mg_residual(f32, lv[l], e[l], R(l), RES(l), s), "mg residual");
-            HIP_TRY(launch_mg_restrict(f32, lv[l], lv[l + 1], tabs[l], RES(l), R(l + 1), s),
+            HIP_TRY(launch_mg_restrict(f32, lv[l], lv[l + 1], tabs[l], RES(l), R(l + 1),
+                                       base + rtmp_off, s),
                     "mg restrict");
         }
         HIP_TRY(zero(nlev - 1), "memset");

@@ -160,9 +160,13 @@ bool mg_build_tables(bool fp32, const Geom &fine, std::vector<unsigned char> &by
 // res = r - ((6*c) - s) (e padded; r, res interior-only).
 hipError_t launch_mg_residual(bool fp32, const Geom &g, const void *e, const void *r, void *res,
                               hipStream_t s);
-// rc = scale * P^T res (interior-only; coarse has ghost width 1).
+// rc = scale * P^T res (interior-only; coarse has ghost width 1).  tmp:
+// device workspace of mg_restrict_tmp_bytes(fp32, fine, coarse) bytes for
+// the per-axis partial sums.
+size_t mg_restrict_tmp_bytes(bool fp32, const Geom &fine, const Geom &coarse);
 hipError_t launch_mg_restrict(bool fp32, const Geom &fine, const Geom &coarse,
-                              const MgTables &tab, const void *res, void *rc, hipStream_t s);
+                              const MgTables &tab, const void *res, void *rc, void *tmp,
+                              hipStream_t s);
 // ef += P ec (both padded).
 hipError_t launch_mg_prolong(bool fp32, const Geom &fine, const Geom &coarse, const MgTables &tab,
                              void *ef, const void *ec, hipStream_t s);

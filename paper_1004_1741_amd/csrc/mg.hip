@@ -6,7 +6,8 @@
 // glue between levels, all elementwise and HBM-bound:
 //
 //   * level residual   res = r - ((6*c) - s)         (precision of the level)
-//   * restriction      r_c = scale * P^T res          (coarse right-hand side)
+//   * restriction      r_c = scale * P^T res          (coarse right-hand side,
+//                                                      one pass per axis)
 //   * prolongation     e_f = e_f + P e_c              (trilinear interpolation)
 //
 // Levels: n interior points per axis at x_i = i/(n+1); the next level has
@@ -90,53 +91,101 @@ __device__ __forceinline__ T axis_w(const MgAxisDev<T> &a, int i, int I) {
     return I == i0 ? a.wm[i] : (I == i0 + 1 ? a.wq[i] : T(0));
 }
 
-// r_c = scale * P^T res (both interior-only); one wave per coarse row.  The
-// weights of a coarse point's fine support (at most MG_MAXS points per axis)
-// are read once into registers: the y and z ones are the same for the whole
-// wave, the x ones per lane.
+// r_c = scale * P^T res (both interior-only), as three one-axis passes that
+// keep the evaluation order: the x sums of every fine row (X: fine z, fine
+// y, coarse x), the y sums of those (Y: fine z, coarse y, coarse x), then the
+// z sums times scale.  Each pass reads its input about once (a fine value
+// lies in the support of at most two coarse points per axis), where one
+// kernel gathering the whole 3-d support per coarse point read every fine
+// residual about eight times through L2.
+//
+// x pass: one wave per run of MG_XR fine rows of one plane, lanes over coarse
+// x; a lane reads its x weights once for the run.
+constexpr int MG_XR = 8;
 template <typename T>
-__global__ void __launch_bounds__(256) mg_restrict_kernel(MgArgs<T> M,
-                                                          const T *__restrict__ res,
-                                                          T *__restrict__ rc) {
+__global__ void __launch_bounds__(256) mg_restrict_x_kernel(MgArgs<T> M,
+                                                            const T *__restrict__ res,
+                                                            T *__restrict__ X) {
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int rows_per_plane = (M.cny + 3) / 4;
-    const int K = blockIdx.x / rows_per_plane + 1;
-    const int J = (blockIdx.x - (K - 1) * rows_per_plane) * 4 + w + 1;
-    if (J > M.cny) return;
-    const MgAxisDev<T> &ax = M.ax[0], &ay = M.ax[1], &az = M.ax[2];
-    const int j0 = ay.lo[J], nj = ay.hi[J] - j0 + 1, k0 = az.lo[K], nk = az.hi[K] - k0 + 1;
-    T wy[MG_MAXS], wz[MG_MAXS];
-#pragma unroll
-    for (int q = 0; q < MG_MAXS; ++q) {
-        wy[q] = q < nj ? axis_w(ay, j0 + q, J) : T(0);
-        wz[q] = q < nk ? axis_w(az, k0 + q, K) : T(0);
-    }
+    const int runs = (M.fny + MG_XR - 1) / MG_XR;
+    const int per_plane = (runs + 3) / 4;
+    const int k = blockIdx.x / per_plane;  // fine plane, 0-based
+    const int run = (blockIdx.x - k * per_plane) * 4 + w;
+    if (run >= runs) return;
+    const int j_lo = run * MG_XR, j_hi = min(j_lo + MG_XR, M.fny);  // fine rows, 0-based
+    const MgAxisDev<T> &ax = M.ax[0];
     for (int I = lane + 1; I <= M.cnx; I += 64) {
         const int i0 = ax.lo[I], ni = ax.hi[I] - i0 + 1;
         T wx[MG_MAXS];
 #pragma unroll
         for (int q = 0; q < MG_MAXS; ++q) wx[q] = q < ni ? axis_w(ax, i0 + q, I) : T(0);
+        for (int j = j_lo; j < j_hi; ++j) {
+            const T *row = res + ((int64_t)k * M.fny + j) * M.fnx + (i0 - 1);
+            T xs = T(0);
+#pragma unroll
+            for (int a = 0; a < MG_MAXS; ++a) {
+                if (a >= ni) break;
+                xs = xs + (wx[a] * row[a]);
+            }
+            X[((int64_t)k * M.fny + j) * M.cnx + (I - 1)] = xs;
+        }
+    }
+}
+
+// y pass: one wave per (fine plane, coarse row), lanes over coarse x.
+template <typename T>
+__global__ void __launch_bounds__(256) mg_restrict_y_kernel(MgArgs<T> M,
+                                                            const T *__restrict__ X,
+                                                            T *__restrict__ Y) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int rows_per_plane = (M.cny + 3) / 4;
+    const int k = blockIdx.x / rows_per_plane;  // fine plane, 0-based
+    const int J = (blockIdx.x - k * rows_per_plane) * 4 + w + 1;
+    if (J > M.cny) return;
+    const MgAxisDev<T> &ay = M.ax[1];
+    const int j0 = ay.lo[J], nj = ay.hi[J] - j0 + 1;
+    T wy[MG_MAXS];
+#pragma unroll
+    for (int q = 0; q < MG_MAXS; ++q) wy[q] = q < nj ? axis_w(ay, j0 + q, J) : T(0);
+    const T *xin = X + ((int64_t)k * M.fny + (j0 - 1)) * M.cnx;
+    T *out = Y + ((int64_t)k * M.cny + (J - 1)) * M.cnx;
+    for (int I = lane; I < M.cnx; I += 64) {
+        T ys = T(0);
+#pragma unroll
+        for (int b = 0; b < MG_MAXS; ++b) {
+            if (b >= nj) break;
+            ys = ys + (wy[b] * xin[(int64_t)b * M.cnx + I]);
+        }
+        out[I] = ys;
+    }
+}
+
+// z pass: one wave per coarse row (K, J), lanes over coarse x.
+template <typename T>
+__global__ void __launch_bounds__(256) mg_restrict_z_kernel(MgArgs<T> M,
+                                                            const T *__restrict__ Y,
+                                                            T *__restrict__ rc) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int rows_per_plane = (M.cny + 3) / 4;
+    const int K = blockIdx.x / rows_per_plane + 1;
+    const int J = (blockIdx.x - (K - 1) * rows_per_plane) * 4 + w + 1;
+    if (J > M.cny) return;
+    const MgAxisDev<T> &az = M.ax[2];
+    const int k0 = az.lo[K], nk = az.hi[K] - k0 + 1;
+    T wz[MG_MAXS];
+#pragma unroll
+    for (int q = 0; q < MG_MAXS; ++q) wz[q] = q < nk ? axis_w(az, k0 + q, K) : T(0);
+    const int64_t zstride = (int64_t)M.cny * M.cnx;
+    const T *yin = Y + ((int64_t)(k0 - 1) * M.cny + (J - 1)) * M.cnx;
+    T *out = rc + ((int64_t)(K - 1) * M.cny + (J - 1)) * M.cnx;
+    for (int I = lane; I < M.cnx; I += 64) {
         T zs = T(0);
 #pragma unroll
         for (int c = 0; c < MG_MAXS; ++c) {
             if (c >= nk) break;
-            T ys = T(0);
-#pragma unroll
-            for (int b = 0; b < MG_MAXS; ++b) {
-                if (b >= nj) break;
-                const T *row = res + ((int64_t)(k0 + c - 1) * M.fny + (j0 + b - 1)) * M.fnx +
-                               (i0 - 1);
-                T xs = T(0);
-#pragma unroll
-                for (int a = 0; a < MG_MAXS; ++a) {
-                    if (a >= ni) break;
-                    xs = xs + (wx[a] * row[a]);
-                }
-                ys = ys + (wy[b] * xs);
-            }
-            zs = zs + (wz[c] * ys);
+            zs = zs + (wz[c] * yin[c * zstride + I]);
         }
-        rc[((int64_t)(K - 1) * M.cny + (J - 1)) * M.cnx + (I - 1)] = zs * M.scale;
+        out[I] = zs * M.scale;
     }
 }
 
@@ -155,6 +204,8 @@ __global__ void __launch_bounds__(256) mg_prolong_kernel(MgArgs<T> M, T *__restr
     const T wmy = ay.wm[j], wqy = ay.wq[j], wmz = az.wm[k], wqz = az.wq[k];
     T *out = ef + (int64_t)(k - 1 + M.fh) * M.fplane + (int64_t)(j - 1 + M.fh) * M.fpx +
              (M.fh - 1);
+    // unrolled so that several points' table and coarse loads are in flight
+#pragma unroll 4
     for (int i = lane + 1; i <= M.fnx; i += 64) {
         const int I0 = ax.i0[i];
         const T wmx = ax.wm[i], wqx = ax.wq[i];
@@ -272,19 +323,35 @@ hipError_t launch_mg_residual(bool fp32, const Geom &g, const void *e, const voi
     return hipGetLastError();
 }
 
-hipError_t launch_mg_restrict(bool fp32, const Geom &fine, const Geom &coarse,
-                              const MgTables &tab, const void *res, void *rc, hipStream_t s) {
-    const double scale = mg_scale(fine);
-    const dim3 grid(rows_grid(coarse.ny, coarse.nz));
-    if (fp32)
-        hipLaunchKernelGGL(mg_restrict_kernel<float>, grid, dim3(256), 0, s,
-                           make_mg_args<float>(fine, coarse, tab, scale), (const float *)res,
-                           (float *)rc);
-    else
-        hipLaunchKernelGGL(mg_restrict_kernel<double>, grid, dim3(256), 0, s,
-                           make_mg_args<double>(fine, coarse, tab, scale), (const double *)res,
-                           (double *)rc);
+size_t mg_restrict_tmp_bytes(bool fp32, const Geom &fine, const Geom &coarse) {
+    const size_t x = (size_t)fine.nz * fine.ny * coarse.nx, y = (size_t)fine.nz * coarse.ny * coarse.nx;
+    return (x + y) * (fp32 ? sizeof(float) : sizeof(double));
+}
+
+template <typename T>
+hipError_t restrict_t(const Geom &fine, const Geom &coarse, const MgTables &tab, const T *res,
+                      T *rc, T *tmp, hipStream_t s) {
+    const MgArgs<T> M = make_mg_args<T>(fine, coarse, tab, mg_scale(fine));
+    T *X = tmp;
+    T *Y = tmp + (size_t)fine.nz * fine.ny * coarse.nx;
+    const int runs = (fine.ny + MG_XR - 1) / MG_XR;
+    hipLaunchKernelGGL(mg_restrict_x_kernel<T>, dim3((unsigned)fine.nz * ((runs + 3) / 4)),
+                       dim3(256), 0, s, M, res, X);
+    hipLaunchKernelGGL(mg_restrict_y_kernel<T>, dim3(rows_grid(coarse.ny, fine.nz)), dim3(256), 0,
+                       s, M, (const T *)X, Y);
+    hipLaunchKernelGGL(mg_restrict_z_kernel<T>, dim3(rows_grid(coarse.ny, coarse.nz)), dim3(256),
+                       0, s, M, (const T *)Y, rc);
     return hipGetLastError();
+}
+
+hipError_t launch_mg_restrict(bool fp32, const Geom &fine, const Geom &coarse,
+                              const MgTables &tab, const void *res, void *rc, void *tmp,
+                              hipStream_t s) {
+    if (fp32)
+        return restrict_t<float>(fine, coarse, tab, (const float *)res, (float *)rc, (float *)tmp,
+                                 s);
+    return restrict_t<double>(fine, coarse, tab, (const double *)res, (double *)rc,
+                              (double *)tmp, s);
 }
 
 hipError_t launch_mg_prolong(bool fp32, const Geom &fine, const Geom &coarse, const MgTables &tab,
