@@ -291,16 +291,17 @@ __device__ __forceinline__ void jacobi_tile(const JacArgs<T> &A, int tx, int ty,
     constexpr bool BUF_STORE = VX == 1 && !(sizeof(T) == 8 && TB == 4 && HAS_F);
     // Row-major steady-state steps (step_rows) where they measured faster on
     // MI355X at 512^3: tiles of one site per lane (two per lane were slower),
-    // three or more levels, with a right-hand side only from five levels up
-    // and with the f ring (per-level f loads were slower), and not for the
-    // plain FP32 depth-4 pass.  In edge tiles they reset the ghost sites next
+    // three or more levels, with a right-hand side only with the f ring and
+    // from five levels up, or at four in FP32 (per-level f loads were
+    // slower), and not for the plain FP32 depth-4 Jacobi pass.  In edge tiles they reset the ghost sites next
     // to the interior once per step (GHOST_RESET).  From five levels in FP64
     // and six in FP32 (EDGE_ASM) edge tiles load through buffer loads that
     // return 0 for sites outside the array and do the reset in asm without
     // compiler-visible branches; below that, loads from clamped addresses and
     // a branch per reset measured faster (FP64 t=3/4 by 2-3 %, FP32 t=5 by 2 %).
-    constexpr bool ROWS = VX == 1 && TB >= 3 && (!HAS_F || (RING && TB >= 5)) &&
-                          !(sizeof(T) == 4 && TB == 4 && !RB);
+    constexpr bool ROWS = VX == 1 && TB >= 3 &&
+                          (!HAS_F || (RING && (TB >= 5 || (sizeof(T) == 4 && TB == 4)))) &&
+                          !(sizeof(T) == 4 && TB == 4 && !RB && !HAS_F);
     constexpr bool GHOST_RESET = ROWS && EDGE;
     constexpr bool EDGE_ASM = GHOST_RESET && TB >= (sizeof(T) == 8 ? 5 : 6);
     constexpr bool EDGE_BUF_LOAD = EDGE_ASM;
@@ -941,7 +942,7 @@ template <> struct Cfg<double, 6, true> { static constexpr int VX = 1, RY = 5, N
 template <> struct Cfg<double, 7, true> { static constexpr int VX = 1, RY = 4, NW = 8; };
 template <> struct Cfg<double, 8, true> { static constexpr int VX = 1, RY = 4, NW = 8; };
 template <> struct Cfg<float, 3, true> { static constexpr int VX = 2, RY = 6, NW = 8; };
-template <> struct Cfg<float, 4, true> { static constexpr int VX = 2, RY = 6, NW = 8; };
+template <> struct Cfg<float, 4, true> { static constexpr int VX = 1, RY = 8, NW = 8; };
 template <> struct Cfg<float, 5, true> { static constexpr int VX = 1, RY = 8, NW = 8; };
 template <> struct Cfg<float, 6, true> { static constexpr int VX = 1, RY = 8, NW = 8; };
 template <> struct Cfg<float, 7, true> { static constexpr int VX = 1, RY = 6, NW = 8; };
