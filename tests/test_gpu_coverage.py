@@ -22,8 +22,8 @@ from gpu_util import assert_same, say, to_dev, to_host, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
-# 252 x 190 x 13: every (dtype, levels, rhs) tiling has interior and edge tiles
-COVER = (252, 190, 13)
+# 252 x 254 x 13: every (dtype, levels, rhs) tiling has interior and edge tiles
+COVER = (252, 254, 13)
 WEIGHTS = [  # (a, b, g, use_f)
     (0.0, 1.0 / 6.0, 0.0, False),
     (0.3, 0.1, 0.25, True),
