@@ -291,16 +291,16 @@ __device__ __forceinline__ void jacobi_tile(const JacArgs<T> &A, int tx, int ty,
     constexpr bool BUF_STORE = VX == 1 && !(sizeof(T) == 8 && TB == 4 && HAS_F);
     // Row-major steady-state steps (step_rows) where they measured faster on
     // MI355X at 512^3: tiles of one site per lane (two per lane were slower),
-    // two or more levels, with a right-hand side only with the f ring and in
-    // FP64 at two levels or from five up (per-level f loads, and the FP64
-    // three- and four-level tiles with f, were slower), and not for the plain
-    // FP32 depth-4 Jacobi pass.  In edge tiles they reset the ghost sites next
+    // two or more levels (FP32: any number), with a right-hand side only with
+    // the f ring and in FP64 at two levels or from five up (per-level f loads,
+    // and the FP64 three- and four-level tiles with f, were slower), and not
+    // for the plain FP32 depth-4 Jacobi pass.  In edge tiles they reset the ghost sites next
     // to the interior once per step (GHOST_RESET).  From five levels in FP64
     // and six in FP32 (EDGE_ASM) edge tiles load through buffer loads that
     // return 0 for sites outside the array and do the reset in asm without
     // compiler-visible branches; below that, loads from clamped addresses and
     // a branch per reset measured faster (FP64 t=3/4 by 2-3 %, FP32 t=5 by 2 %).
-    constexpr bool ROWS = VX == 1 && TB >= 2 &&
+    constexpr bool ROWS = VX == 1 && (TB >= 2 || sizeof(T) == 4) &&
                           (!HAS_F || (RING && (TB >= 5 || TB == 2 || sizeof(T) == 4))) &&
                           !(sizeof(T) == 4 && TB == 4 && !RB && !HAS_F);
     constexpr bool GHOST_RESET = ROWS && EDGE;
@@ -922,7 +922,7 @@ template <> struct CfgBase<double, 5> { static constexpr int VX = 1, RY = 7, NW 
 template <> struct CfgBase<double, 6> { static constexpr int VX = 1, RY = 6, NW = 8; };
 template <> struct CfgBase<double, 7> { static constexpr int VX = 1, RY = 5, NW = 8; };
 template <> struct CfgBase<double, 8> { static constexpr int VX = 1, RY = 5, NW = 8; };
-template <> struct CfgBase<float, 1> { static constexpr int VX = 2, RY = 8, NW = 8; };
+template <> struct CfgBase<float, 1> { static constexpr int VX = 1, RY = 16, NW = 8; };
 template <> struct CfgBase<float, 2> { static constexpr int VX = 1, RY = 16, NW = 8; };
 template <> struct CfgBase<float, 3> { static constexpr int VX = 1, RY = 12, NW = 8; };
 template <> struct CfgBase<float, 4> { static constexpr int VX = 1, RY = 12, NW = 8; };
