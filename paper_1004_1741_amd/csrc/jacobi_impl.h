@@ -928,7 +928,7 @@ template <> struct CfgBase<float, 3> { static constexpr int VX = 1, RY = 12, NW 
 template <> struct CfgBase<float, 4> { static constexpr int VX = 1, RY = 12, NW = 8; };
 template <> struct CfgBase<float, 5> { static constexpr int VX = 1, RY = 12, NW = 8; };
 template <> struct CfgBase<float, 6> { static constexpr int VX = 1, RY = 8, NW = 8; };
-template <> struct CfgBase<float, 7> { static constexpr int VX = 1, RY = 8, NW = 8; };
+template <> struct CfgBase<float, 7> { static constexpr int VX = 1, RY = 9, NW = 8; };
 template <> struct CfgBase<float, 8> { static constexpr int VX = 1, RY = 8, NW = 8; };
 // With a right-hand side the prefetched f planes add register pressure and
 // the f ring needs LDS next to the exchange buffer: some shapes are shorter
@@ -947,7 +947,7 @@ template <> struct Cfg<float, 3, true> { static constexpr int VX = 1, RY = 8, NW
 template <> struct Cfg<float, 4, true> { static constexpr int VX = 1, RY = 8, NW = 8; };
 template <> struct Cfg<float, 5, true> { static constexpr int VX = 1, RY = 8, NW = 8; };
 template <> struct Cfg<float, 6, true> { static constexpr int VX = 1, RY = 8, NW = 8; };
-template <> struct Cfg<float, 7, true> { static constexpr int VX = 1, RY = 6, NW = 8; };
+template <> struct Cfg<float, 7, true> { static constexpr int VX = 1, RY = 8, NW = 8; };
 template <> struct Cfg<float, 8, true> { static constexpr int VX = 1, RY = 6, NW = 8; };
 
 template <typename T, int TB, bool HAS_F = false>
