@@ -68,6 +68,24 @@ def test_refine_fp32_inner_fixed_steps(P, olib, method):
     assert abs(grel - rel) <= 1e-12 * rel
 
 
+@pytest.mark.parametrize("method,m", [(0, 13), (2, 9)])
+def test_refine_fp32_inner_odd_pass_count(P, olib, method, m):
+    """Inner solves whose fused schedule has an odd number of passes (Jacobi
+    13 = 6 + 6 + 1, red-black 9 = 3 + 3 + 3 at the FP32 defaults): the FP32
+    correction and its scratch grid swap roles instead of a pass being split,
+    and the swap carries into the next rounds.  Bit-exact against the
+    oracle's loop."""
+    u0, fp = _poisson((70, 61, 30), seed=12)
+    ref, rc, outer, rel = oracle.refine(u0, fp, method=method, inner_f32=True, m=m, tol=0.0,
+                                        max_outer=3, lib=olib)
+    du = to_dev(u0)
+    od, grel, grc = P.refine_solve(du, to_dev(fp), method=method, inner_fp32=True,
+                                   inner_sweeps=m, rel_tol=0.0, max_outer=3,
+                                   raise_on_noconv=False)
+    assert grc == -6 and od == 3 and rc == -6 and outer == 3
+    assert_same(to_host(du), ref, "refine fp32 odd passes method=%d m=%d" % (method, m))
+
+
 @pytest.mark.parametrize("method", [0, 1, 2])
 def test_refine_fp32_inner_fixed_steps_192(P, olib, method):
     """Two defect-correction steps on 192^3 (the float inner passes run
