@@ -147,13 +147,13 @@ int run_jacobi(const Geom &g, bool fp32, void *u, void *scratch, const void *f, 
 }
 
 // Red-black sweeps per pass: at most 4 (8 levels on chip).  Automatic: FP64
-// 2, FP32 3.  512^3 on MI355X, 32 sweeps with a right-hand side (the inner
-// solve of the refinement) at 1/2/3/4 sweeps per pass: FP64 23.3/14.4/23.2/
-// 35.8 ms, FP32 17.6/11.6/8.1/9.9 ms; without one, 100 sweeps: FP64 50.2/
-// 25.2/25.3/30.8 ms, FP32 2 and 3 per pass within 1 %.
+// 2 with a right-hand side and 3 without, FP32 3.  512^3 on MI355X, 32 sweeps
+// with a right-hand side (the inner solve of the refinement) at 1/2/3/4
+// sweeps per pass: FP64 23.3/14.4/23.2/35.8 ms, FP32 17.6/11.6/8.1/9.9 ms;
+// without one, 100 sweeps: FP64 50.2/25.2/24.9/30.2 ms, FP32 3 per pass the
+// fastest.
 int rb_sweeps_per_pass(int t_fuse, bool fp32, bool rhs) {
-    (void)rhs;
-    int t = t_fuse == 0 ? (fp32 ? 3 : 2) : t_fuse;
+    int t = t_fuse == 0 ? (fp32 || !rhs ? 3 : 2) : t_fuse;
     return t > 4 ? 4 : t;
 }
 
