@@ -285,10 +285,8 @@ __device__ __forceinline__ void jacobi_tile(const JacArgs<T> &A, int tx, int ty,
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int h = A.h;
     // Row stores as unconditional buffer stores (see the store at the end of
-    // a step) where one point per lane is stored.  The FP64 depth-4 tile with
-    // a right-hand side already sits at the register limit, and the store
-    // offsets make it spill (measured slower), so it keeps plain stores.
-    constexpr bool BUF_STORE = VX == 1 && !(sizeof(T) == 8 && TB == 4 && HAS_F);
+    // a step) where one point per lane is stored.
+    constexpr bool BUF_STORE = VX == 1;
     // Row-major steady-state steps (step_rows) where they measured faster on
     // MI355X at 512^3: tiles of one site per lane (two per lane were slower),
     // two or more levels (FP32: any number), with a right-hand side only with
