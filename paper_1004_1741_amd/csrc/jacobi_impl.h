@@ -944,7 +944,7 @@ template <> struct Cfg<double, 8, true> { static constexpr int VX = 1, RY = 4, N
 template <> struct Cfg<float, 3, true> { static constexpr int VX = 1, RY = 8, NW = 8; };
 template <> struct Cfg<float, 4, true> { static constexpr int VX = 1, RY = 8, NW = 8; };
 template <> struct Cfg<float, 5, true> { static constexpr int VX = 1, RY = 8, NW = 8; };
-template <> struct Cfg<float, 6, true> { static constexpr int VX = 1, RY = 8, NW = 8; };
+template <> struct Cfg<float, 6, true> { static constexpr int VX = 1, RY = 7, NW = 8; };
 template <> struct Cfg<float, 7, true> { static constexpr int VX = 1, RY = 8, NW = 8; };
 template <> struct Cfg<float, 8, true> { static constexpr int VX = 1, RY = 6, NW = 8; };
 
